@@ -1,0 +1,272 @@
+"""Seeded synthetic inputs: problem setups and primitive initial fields.
+
+This module holds none of the scheme's arithmetic.  It only draws random
+numbers and samples closed-form initial conditions at cell centres
+``x_i = lo + (i + 1/2) dx``; each side of a comparison (the HIP library
+and the CPU oracle) converts the returned primitive fields
+``V = (rho, vx, vy, vz, p, Bx, By, Bz, psi)`` to conserved variables with
+its own equation of state.
+
+Arrays are float64, shape ``(9, nz, ny, nx)`` (x fastest).  A *setup* is a
+plain dict naming the grid, the solver options and the run length.
+
+Workloads (the paper benchmarks the 3D Orszag-Tang vortex and the
+circularly polarised Alfven wave, section "Results for gPLUTO"; the setups
+of those runs are not printed, so these are synthetic stand-ins):
+
+* ``brio_wu``      1D Riemann problem, 400 cells, gamma=2, Bx=0.75.
+* ``turbulence``   3D periodic decaying turbulence, seeded Gaussian mode
+                   sums with k^-2 power in 1 <= |k| <= 4, divergence-free B.
+* ``orszag_tang``  2D periodic vortex with seeded +-5% amplitudes.
+* ``cpa_wave``     circularly polarised Alfven wave (exact nonlinear
+                   travelling solution), 1D/2D/3D, any direction.
+* ``sod``, ``uniform``, ``stationary_contact``: closed-form test states.
+"""
+import math
+
+import numpy as np
+
+PERIODIC3 = (("periodic", "periodic"),) * 3
+OUTFLOW_X = (("outflow", "outflow"), ("periodic", "periodic"), ("periodic", "periodic"))
+
+
+def make_setup(name, ndim, n, *, gamma, cfl, riemann="hlld", limiter="minmod", bc=PERIODIC3,
+               glm=True, glm_alpha=0.1, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), nsteps=None,
+               t_end=None):
+    n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
+    return {
+        "name": name, "ndim": int(ndim), "n": n, "lo": tuple(lo), "hi": tuple(hi),
+        "gamma": float(gamma), "cfl": float(cfl), "riemann": riemann, "limiter": limiter,
+        "bc": tuple(tuple(b) for b in bc), "glm": bool(glm), "glm_alpha": float(glm_alpha),
+        "nsteps": nsteps, "t_end": t_end,
+    }
+
+
+def cell_centres(setup):
+    """1D coordinate arrays (x, y, z) of the cell centres."""
+    out = []
+    for d in range(3):
+        n = setup["n"][d]
+        lo, hi = setup["lo"][d], setup["hi"][d]
+        out.append(lo + (np.arange(n) + 0.5) * (hi - lo) / n)
+    return out
+
+
+def _empty(setup):
+    nx, ny, nz = setup["n"]
+    return np.zeros((9, nz, ny, nx))
+
+
+# ---------------------------------------------------------------- 1D -------
+
+def brio_wu(n=400):
+    """Brio & Wu (1988)-type shock tube: gamma=2, Bx=0.75, left (rho,p,By) =
+    (1,1,1), right (0.125,0.1,-1), v=0, Bz=0; outflow; to t=0.1 with
+    minmod + HLL, RK2, CFL 0.4."""
+    s = make_setup("brio_wu", 1, (n,), gamma=2.0, cfl=0.4, riemann="hll", bc=OUTFLOW_X,
+                   t_end=0.1)
+    x = cell_centres(s)[0]
+    V = _empty(s)
+    left = x < 0.5
+    V[0, 0, 0] = np.where(left, 1.0, 0.125)
+    V[4, 0, 0] = np.where(left, 1.0, 0.1)
+    V[5] = 0.75
+    V[6, 0, 0] = np.where(left, 1.0, -1.0)
+    return s, V
+
+
+def sod(n, riemann="hll", gamma=1.4, t_end=0.2):
+    """Sod (1978) shock tube with B = 0: (rho,p) = (1,1) | (0.125,0.1)."""
+    s = make_setup("sod", 1, (n,), gamma=gamma, cfl=0.4, riemann=riemann, bc=OUTFLOW_X,
+                   t_end=t_end)
+    x = cell_centres(s)[0]
+    V = _empty(s)
+    left = x < 0.5
+    V[0, 0, 0] = np.where(left, 1.0, 0.125)
+    V[4, 0, 0] = np.where(left, 1.0, 0.1)
+    return s, V
+
+
+def stationary_contact(n=64, riemann="hlld"):
+    """Isolated contact: density jump, v=0, uniform p and B with Bn != 0."""
+    s = make_setup("contact", 1, (n,), gamma=5.0 / 3.0, cfl=0.4, riemann=riemann,
+                   bc=OUTFLOW_X, nsteps=100)
+    x = cell_centres(s)[0]
+    V = _empty(s)
+    V[0, 0, 0] = np.where(x < 0.5, 1.0, 0.3)
+    V[4] = 1.0
+    V[5] = 1.0
+    V[6] = 0.5
+    V[7] = 0.3
+    return s, V
+
+
+# ------------------------------------------------------------ uniform ------
+
+def uniform(n, ndim=3, state=(1.3, 0.2, -0.3, 0.1, 0.9, 0.7, -0.4, 0.25, 0.0), riemann="hlld",
+            cfl=0.3, gamma=5.0 / 3.0):
+    n = tuple(n) + (1,) * (3 - len(n))
+    s = make_setup("uniform", ndim, n, gamma=gamma, cfl=cfl, riemann=riemann)
+    V = _empty(s)
+    for q in range(9):
+        V[q] = state[q]
+    return s, V
+
+
+# ------------------------------------------------------- Alfven wave -------
+
+def cpa_wave(n, ndim=1, k=(1, 0, 0), amplitude=1e-3, rho=1.0, p=1.0, b0=1.0, riemann="hlld",
+             cfl=0.4, gamma=5.0 / 3.0):
+    """Circularly polarised Alfven wave travelling along +k.
+
+    B = b0 khat + A (sin phi e1 + cos phi e2),  v = -(B - b0 khat)/sqrt(rho),
+    phi = 2 pi k.x; |B| and the total pressure are uniform, so this is an
+    exact travelling solution at speed b0/sqrt(rho) for any amplitude.  One
+    period is 1/|k| / (b0/sqrt(rho)) on the unit box."""
+    n = tuple(n) + (1,) * (3 - len(n))
+    s = make_setup("cpa", ndim, n, gamma=gamma, cfl=cfl, riemann=riemann)
+    k = np.asarray(k, dtype=float)
+    kn = np.linalg.norm(k)
+    kh = k / kn
+    # e1 perpendicular to k in the plane of k and z-hat (or y-hat for k || z)
+    ref = np.array([0.0, 0.0, 1.0]) if abs(kh[2]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(ref, kh)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(kh, e1)
+    x, y, z = cell_centres(s)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    phi = 2 * math.pi * (k[0] * X + k[1] * Y + k[2] * Z)
+    V = _empty(s)
+    V[0] = rho
+    V[4] = p
+    for a in range(3):
+        db = amplitude * (np.sin(phi) * e1[a] + np.cos(phi) * e2[a])
+        V[5 + a] = b0 * kh[a] + db
+        V[1 + a] = -db / math.sqrt(rho)
+    s["period"] = 1.0 / kn / (b0 / math.sqrt(rho))
+    return s, V
+
+
+# -------------------------------------------------------- turbulence -------
+
+def half_space_modes(kmax=4):
+    """Integer wavevectors with 1 <= |k| <= kmax in the half space
+    (kx>0) or (kx=0, ky>0) or (kx=ky=0, kz>0), in lexicographic order."""
+    out = []
+    r = range(-kmax, kmax + 1)
+    for kx in r:
+        for ky in r:
+            for kz in r:
+                k2 = kx * kx + ky * ky + kz * kz
+                if not (1 <= k2 <= kmax * kmax):
+                    continue
+                if kx > 0 or (kx == 0 and ky > 0) or (kx == 0 and ky == 0 and kz > 0):
+                    out.append((kx, ky, kz))
+    return out
+
+
+def _mode_coeffs(seed, power_exp, kmax=4):
+    """Complex 3-vector coefficient c_k = a_k - i b_k per half-space mode,
+    a_k, b_k ~ N(0, |k|^power_exp) componentwise, so that
+    f(x) = sum_k a_k cos(2 pi k.x) + b_k sin(2 pi k.x) = Re sum c_k e^{2 pi i k.x}."""
+    rng = np.random.default_rng(seed)
+    modes = half_space_modes(kmax)
+    coeffs = []
+    for k in modes:
+        std = math.sqrt(float(k[0] ** 2 + k[1] ** 2 + k[2] ** 2) ** power_exp)
+        a = rng.normal(0.0, std, 3)
+        b = rng.normal(0.0, std, 3)
+        coeffs.append(a - 1j * b)
+    return modes, coeffs
+
+
+def _sample_mode_sum(setup, modes, coeffs, kmax=4):
+    """Evaluate Re sum_k c_k e^{2 pi i k.x} (c_k complex 3-vectors) at the
+    cell centres, separably: per axis a (2kmax+1) x n table of e^{2 pi i k x}
+    and two real matrix products.  Returns (3, nz, ny, nx)."""
+    xs = cell_centres(setup)
+    nx, ny, nz = setup["n"]
+    K = 2 * kmax + 1
+    ex = [np.exp(2j * math.pi * (kk - kmax) * xs[0]) for kk in range(K)]
+    ey = [np.exp(2j * math.pi * (kk - kmax) * xs[1]) for kk in range(K)]
+    ez = [np.exp(2j * math.pi * (kk - kmax) * xs[2]) for kk in range(K)]
+    Ex, Ey, Ez = np.array(ex), np.array(ey), np.array(ez)  # (K, n)
+    out = np.empty((3, nz, ny, nx))
+    for a in range(3):
+        C = np.zeros((K, K, K), dtype=complex)  # [kz, ky, kx]
+        for k, c in zip(modes, coeffs):
+            C[k[2] + kmax, k[1] + kmax, k[0] + kmax] += c[a]
+        # G[kz, y, x] = sum_{ky,kx} C[kz,ky,kx] Ey[ky,y] Ex[kx,x]
+        G = np.einsum("zab,ay,bx->zyx", C, Ey, Ex, optimize=True).reshape(K, ny * nx)
+        # f[z, yx] = Re sum_kz Ez[kz, z] G[kz, yx]
+        f = Ez.real.T @ G.real - Ez.imag.T @ G.imag
+        out[a] = f.reshape(nz, ny, nx)
+    return out
+
+
+def turbulence(n, seed_v=1, seed_a=2, vrms=0.5, brms=0.5, riemann="hlld", cfl=0.3, nsteps=100,
+               kmax=4):
+    """3D periodic decaying MHD turbulence on [0,1]^3.
+
+    rho = 1, p = 1, gamma = 5/3, psi = 0.  v is a Gaussian mode sum over the
+    half-space integer wavevectors 1 <= |k| <= kmax with per-mode variance
+    |k|^-2; B = curl A, taken analytically from a mode sum A with variance
+    |k|^-4 (so B has |k|^-2 power and is exactly solenoidal in the
+    continuum).  Both are scaled to the requested rms over the cells."""
+    if isinstance(n, int):
+        n = (n, n, n)
+    s = make_setup("turbulence", 3, n, gamma=5.0 / 3.0, cfl=cfl, riemann=riemann, nsteps=nsteps)
+    modes, cv = _mode_coeffs(seed_v, -1.0, kmax)
+    v = _sample_mode_sum(s, modes, cv, kmax)
+    modes, ca = _mode_coeffs(seed_a, -2.0, kmax)
+    cb = [2j * math.pi * np.cross(np.array(k, dtype=float), c) for k, c in zip(modes, ca)]
+    b = _sample_mode_sum(s, modes, cb, kmax)
+    v *= vrms / math.sqrt(np.mean(np.sum(v * v, axis=0)))
+    b *= brms / math.sqrt(np.mean(np.sum(b * b, axis=0)))
+    V = np.empty((9,) + v.shape[1:])
+    V[0] = 1.0
+    V[1:4] = v
+    V[4] = 1.0
+    V[5:8] = b
+    V[8] = 0.0
+    return s, V
+
+
+def smooth_direction(n, seed, kmax=4):
+    """Smooth random perturbation (3 fields) from the same mode-sum
+    generator, each component scaled to unit rms; used as a direction for
+    finite-difference checks."""
+    if isinstance(n, int):
+        n = (n, n, n)
+    s = make_setup("direction", 3, n, gamma=5.0 / 3.0, cfl=0.3)
+    modes, c = _mode_coeffs(seed, -1.0, kmax)
+    f = _sample_mode_sum(s, modes, c, kmax)
+    for a in range(3):
+        f[a] /= math.sqrt(np.mean(f[a] * f[a]))
+    return f
+
+
+# ------------------------------------------------------- Orszag-Tang -------
+
+def orszag_tang(n=1024, seed=3, riemann="hlld", cfl=0.4, t_end=0.5):
+    """2D periodic Orszag & Tang (1979)-type vortex on [0,1]^2:
+    rho = 25/(36 pi), p = 5/(12 pi), gamma = 5/3,
+    v = (-a1 sin 2pi y, a2 sin 2pi x), B = B0 (-a3 sin 2pi y, a4 sin 4pi x),
+    B0 = 1/sqrt(4 pi), a_i = 1 + 0.05 u_i with u_i ~ U(-1, 1) from the seed."""
+    if isinstance(n, int):
+        n = (n, n)
+    s = make_setup("orszag_tang", 2, n, gamma=5.0 / 3.0, cfl=cfl, riemann=riemann, t_end=t_end)
+    rng = np.random.default_rng(seed)
+    a = 1.0 + 0.05 * rng.uniform(-1.0, 1.0, 4)
+    x, y, _ = cell_centres(s)
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    b0 = 1.0 / math.sqrt(4 * math.pi)
+    V = _empty(s)
+    V[0] = 25.0 / (36.0 * math.pi)
+    V[1, 0] = -a[0] * np.sin(2 * math.pi * Y)
+    V[2, 0] = a[1] * np.sin(2 * math.pi * X)
+    V[4] = 5.0 / (12.0 * math.pi)
+    V[5, 0] = -b0 * a[2] * np.sin(2 * math.pi * Y)
+    V[6, 0] = b0 * a[3] * np.sin(4 * math.pi * X)
+    s["amplitudes"] = a.tolist()
+    return s, V

@@ -1,0 +1,319 @@
+"""Pins of the oracle's pointwise pieces against closed forms.
+
+Each check comes from the mathematics of the published method, not from
+the oracle itself:
+* limiter: exact slope on linear data, zero at extrema (van Leer 1979);
+* fast magnetosonic speed: sqrt(a^2+b^2) across B, max(a,b) along B;
+* GLM interface state: the two characteristic variables psi +/- c_h B_n are
+  carried from the upwind side (Dedner et al. 2002);
+* Riemann solvers: consistency F(V,V) = physical flux (textbook vector
+  form written here), upwinding for supersonic states, the HLLD integral
+  consistency condition and exact resolution of isolated contact,
+  tangential and rotational discontinuities (Miyoshi & Kusano 2005).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import coracle as C
+from paper_2510_24175_amd import workloads as W
+
+GAMMA = 5.0 / 3.0
+
+
+def textbook_flux(V, d, gamma, ch=None):
+    """Physical ideal-MHD flux along axis d in vector form (9 comps)."""
+    rho, v, p, B, psi = V[0], np.array(V[1:4]), V[4], np.array(V[5:8]), V[8]
+    n = np.zeros(3)
+    n[d] = 1.0
+    vn, bn = v @ n, B @ n
+    pt = p + 0.5 * (B @ B)
+    E = p / (gamma - 1) + 0.5 * rho * (v @ v) + 0.5 * (B @ B)
+    F = np.zeros(9)
+    F[0] = rho * vn
+    F[1:4] = rho * v * vn + pt * n - B * bn
+    F[4] = (E + pt) * vn - bn * (v @ B)
+    F[5:8] = vn * B - bn * v
+    if ch is not None:  # GLM: normal-field flux psi, psi flux ch^2 Bn
+        F[5 + d] = psi
+        F[8] = ch * ch * bn
+    return F
+
+
+def random_state(rng, with_psi=True):
+    V = np.empty(9)
+    V[0] = rng.uniform(0.3, 2.0)
+    V[1:4] = rng.uniform(-0.6, 0.6, 3)
+    V[4] = rng.uniform(0.2, 2.0)
+    V[5:8] = rng.uniform(-1.2, 1.2, 3)
+    V[8] = rng.uniform(-0.2, 0.2) if with_psi else 0.0
+    return V
+
+
+def rot_state(V, d):
+    """(rho, u, vt1, vt2, p, Bn, Bt1, Bt2) for the cyclic frame of axis d."""
+    ax = [d, (d + 1) % 3, (d + 2) % 3]
+    return np.array([V[0], V[1 + ax[0]], V[1 + ax[1]], V[1 + ax[2]], V[4],
+                     V[5 + ax[0]], V[5 + ax[1]], V[5 + ax[2]]])
+
+
+def rot_flux_textbook(q, gamma):
+    """Rotated-frame physical flux of (rho,u,v1,v2,p,Bn,B1,B2), 8 comps."""
+    V = np.array([q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], 0.0])
+    F = textbook_flux(V, 0, gamma)
+    return F[:8]
+
+
+def rot_cons(q, gamma):
+    rho, u, v1, v2, p, bn, b1, b2 = q
+    E = p / (gamma - 1) + 0.5 * rho * (u * u + v1 * v1 + v2 * v2) + 0.5 * (bn * bn + b1 * b1 + b2 * b2)
+    return np.array([rho, rho * u, rho * v1, rho * v2, E, bn, b1, b2])
+
+
+# ------------------------------------------------------------ limiter ------
+
+@pytest.mark.parametrize("lim", ["minmod", "mc"])
+def test_limiter_linear_data_gives_exact_slope(lim):
+    for a in [0.5, -2.0, 1e-3, 3.25]:
+        assert C.limited_slope(lim, a, a) == a
+
+
+def test_limiter_closed_forms():
+    # extremum or flat side: zero slope
+    for a, b in [(1.0, -1.0), (-0.5, 2.0), (0.0, 1.0), (1.0, 0.0)]:
+        assert C.limited_slope("minmod", a, b) == 0.0
+        assert C.limited_slope("mc", a, b) == 0.0
+    # minmod picks the smaller magnitude with the common sign
+    assert C.limited_slope("minmod", 1.0, 3.0) == 1.0
+    assert C.limited_slope("minmod", -4.0, -0.5) == -0.5
+    # MC: min(2|a|, 2|b|, |a+b|/2)
+    assert C.limited_slope("mc", 1.0, 3.0) == 2.0
+    assert C.limited_slope("mc", 1.0, 1.5) == 1.25
+    assert C.limited_slope("mc", -0.1, -5.0) == -0.2
+
+
+def test_limiter_tvd_on_monotone_step():
+    """Face values of a limited monotone profile stay within the neighbours."""
+    rng = np.random.default_rng(0)
+    v = np.sort(rng.uniform(0, 1, 40))
+    for i in range(1, 39):
+        for lim in ["minmod", "mc"]:
+            s = C.limited_slope(lim, v[i] - v[i - 1], v[i + 1] - v[i])
+            assert v[i - 1] - 1e-15 <= v[i] - 0.5 * s <= v[i] + 1e-15
+            assert v[i] - 1e-15 <= v[i] + 0.5 * s <= v[i + 1] + 1e-15
+
+
+# --------------------------------------------------------- fast speed ------
+
+def test_fast_speed_closed_forms():
+    rho, p, g = 1.7, 0.9, GAMMA
+    a2 = g * p / rho
+    for d in range(3):
+        # B perpendicular to d
+        V = np.array([rho, 0, 0, 0, p, 0, 0, 0, 0], dtype=float)
+        V[5 + (d + 1) % 3] = 0.8
+        V[5 + (d + 2) % 3] = -0.3
+        b2 = (0.64 + 0.09) / rho
+        assert C.fast_speed(V, g, d) == pytest.approx(math.sqrt(a2 + b2), rel=1e-15)
+        # B along d, both orderings of a and b
+        for bd in [0.4, 2.5]:
+            V = np.array([rho, 0, 0, 0, p, 0, 0, 0, 0], dtype=float)
+            V[5 + d] = bd
+            expect = max(math.sqrt(a2), bd / math.sqrt(rho))
+            assert C.fast_speed(V, g, d) == pytest.approx(expect, rel=1e-14)
+        # no field: sound speed
+        V = np.array([rho, 0.3, 0, 0, p, 0, 0, 0, 0], dtype=float)
+        assert C.fast_speed(V, g, d) == pytest.approx(math.sqrt(a2), rel=1e-15)
+
+
+# ---------------------------------------------------------------- GLM ------
+
+def test_glm_characteristic_invariants():
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        bl, br, pl, pr = rng.normal(size=4)
+        ch = rng.uniform(0.1, 5.0)
+        bs, ps = C.glm_interface(bl, br, pl, pr, ch)
+        # psi + ch Bn is carried from the left, psi - ch Bn from the right
+        assert ps + ch * bs == pytest.approx(pl + ch * bl, abs=1e-14 * (1 + ch))
+        assert ps - ch * bs == pytest.approx(pr - ch * br, abs=1e-14 * (1 + ch))
+
+
+# ----------------------------------------------------------- solvers -------
+
+@pytest.mark.parametrize("riemann", ["hll", "hlld"])
+@pytest.mark.parametrize("glm", [True, False])
+def test_consistency_equal_states(riemann, glm):
+    rng = np.random.default_rng(2)
+    s = W.make_setup("t", 3, (4, 4, 4), gamma=GAMMA, cfl=0.3, riemann=riemann, glm=glm)
+    o = C.Oracle(s)
+    for _ in range(100):
+        V = random_state(rng, with_psi=glm)
+        ch = rng.uniform(0.5, 4.0)
+        for d in range(3):
+            F = C.face_flux(o, d, V, V, ch)
+            ref = textbook_flux(V, d, GAMMA, ch if glm else None)
+            if not glm:
+                ref[8] = 0.0
+            scale = np.abs(ref).max() + 1.0
+            np.testing.assert_allclose(F, ref, rtol=0, atol=2e-14 * scale)
+
+
+@pytest.mark.parametrize("riemann", ["hll", "hlld"])
+def test_supersonic_states_take_upwind_flux(riemann):
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        qL = rot_state(random_state(rng), 0)
+        qR = rot_state(random_state(rng), 0)
+        qR[5] = qL[5]
+        for sign in [+1, -1]:
+            a, b = qL.copy(), qR.copy()
+            a[1] += sign * 20.0
+            b[1] += sign * 20.0  # everything moves faster than any wave
+            F = C.rotated_flux(riemann, a, b, GAMMA)
+            up = a if sign > 0 else b
+            ref = rot_flux_textbook(up, GAMMA)
+            ref[5] = 0.0
+            np.testing.assert_allclose(F, ref, rtol=1e-14, atol=1e-13)
+
+
+def _fan_cases(rng, n):
+    for _ in range(n):
+        qL = rot_state(random_state(rng), 0)
+        qR = rot_state(random_state(rng), 0)
+        qR[5] = qL[5]
+        yield qL, qR
+    # switch-on type degenerate case: no tangential field, strong Bn
+    yield (np.array([1.0, 0.1, 0.0, 0.0, 0.2, 2.0, 0.0, 0.0]),
+           np.array([0.5, -0.1, 0.3, 0.0, 0.1, 2.0, 0.0, 0.0]))
+    # zero normal field: HLLC-like fan with an empty double-star region
+    yield (np.array([1.0, 0.3, 0.2, -0.1, 1.0, 0.0, 0.5, 0.2]),
+           np.array([0.3, -0.2, 0.0, 0.4, 0.5, 0.0, -0.4, 0.1]))
+
+
+def test_hlld_integral_consistency():
+    """The HLLD fan integrates to the HLL average state:
+    sum over the four intermediate states of (width x state)
+    = S_R U_R - S_L U_L - (F_R - F_L), with ordered speeds."""
+    rng = np.random.default_rng(4)
+    for qL, qR in _fan_cases(rng, 300):
+        f = C.hlld_fan(qL, qR, GAMMA)
+        sL, ssL, sM, ssR, sR = f["s"]
+        assert sL < sM < sR
+        assert ssL <= sM <= ssR
+        # S*_a lies inside the outer fan iff D_a = rho_a (S_a-u_a)(S_a-S_M) - Bn^2 >= 0
+        for s_out, s_in, q in [(sL, ssL, qL), (sR, ssR, qR)]:
+            D = q[0] * (s_out - q[1]) * (s_out - sM) - q[5] ** 2
+            if D > 1e-12:
+                assert abs(s_in - sM) <= abs(s_out - sM) + 1e-14
+        UL, UR = rot_cons(qL, GAMMA), rot_cons(qR, GAMMA)
+        FL, FR = rot_flux_textbook(qL, GAMMA), rot_flux_textbook(qR, GAMMA)
+        np.testing.assert_allclose(f["UL"], UL, rtol=1e-15, atol=1e-15)
+        np.testing.assert_allclose(f["FL"][[0, 1, 2, 3, 4, 6, 7]], FL[[0, 1, 2, 3, 4, 6, 7]],
+                                   rtol=1e-14, atol=1e-14)
+        lhs = ((ssL - sL) * f["UsL"] + (sM - ssL) * f["UssL"] + (ssR - sM) * f["UssR"]
+               + (sR - ssR) * f["UsR"])
+        rhs = sR * UR - sL * UL - (FR - FL)
+        rhs[5] = (sR - sL) * qL[5]  # the normal field is constant across the fan
+        scale = np.abs(rhs).max() + np.abs(sR - sL) * np.abs(UL).max()
+        np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-13 * scale)
+
+
+def test_hlld_resolves_isolated_contact_exactly():
+    qL = np.array([1.0, 0.0, 0.0, 0.0, 0.8, 0.9, 0.5, -0.3])
+    qR = qL.copy()
+    qR[0] = 0.25
+    ref = rot_flux_textbook(qL, GAMMA)
+    ref[5] = 0.0
+    np.testing.assert_allclose(C.rotated_flux("hlld", qL, qR, GAMMA), ref, rtol=1e-14, atol=1e-15)
+    # HLL smears it: the mass flux is non-zero
+    assert abs(C.rotated_flux("hll", qL, qR, GAMMA)[0]) > 1e-3
+
+
+def test_hlld_resolves_tangential_discontinuity_exactly():
+    qL = np.array([1.0, 0.0, 0.3, 0.0, 1.0, 0.0, 0.5, 0.2])
+    bR = np.array([-0.3, 0.6])
+    pR = 1.0 + 0.5 * (0.25 + 0.04) - 0.5 * (bR @ bR)
+    qR = np.array([0.4, 0.0, -0.2, 0.5, pR, 0.0, bR[0], bR[1]])
+    F = C.rotated_flux("hlld", qL, qR, GAMMA)
+    pt = 1.0 + 0.5 * (0.25 + 0.04)
+    ref = np.array([0, pt, 0, 0, 0, 0, 0, 0])
+    np.testing.assert_allclose(F, ref, rtol=0, atol=2e-15)
+
+
+@pytest.mark.parametrize("side", ["left", "right"])
+@pytest.mark.parametrize("bn", [0.9, -0.7])
+def test_hlld_resolves_rotational_discontinuity_exactly(side, bn):
+    """A single Alfven discontinuity (|B_t| kept, dv_t = -/+ sgn(Bn) dB_t/sqrt(rho))
+    moving at S*_L < 0 (or S*_R > 0) gives F = F_R (or F_L): the
+    Rankine-Hugoniot flux of the exact solution at x/t = 0."""
+    rho, p = 1.3, 0.8
+    sgn = 1.0 if bn >= 0 else -1.0
+    ca = abs(bn) / math.sqrt(rho)
+    bt = np.array([0.6, 0.3])
+    th = 1.1
+    rot = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    btR = rot @ bt
+    vtL = np.array([0.1, -0.2])
+    if side == "left":
+        u = ca - 0.3  # wave speed u - ca = -0.3
+        vtR = vtL + sgn * (btR - bt) / math.sqrt(rho)
+    else:
+        u = -ca + 0.25  # wave speed u + ca = +0.25
+        vtR = vtL - sgn * (btR - bt) / math.sqrt(rho)
+    qL = np.array([rho, u, vtL[0], vtL[1], p, bn, bt[0], bt[1]])
+    qR = np.array([rho, u, vtR[0], vtR[1], p, bn, btR[0], btR[1]])
+    F = C.rotated_flux("hlld", qL, qR, GAMMA)
+    ref = rot_flux_textbook(qR if side == "left" else qL, GAMMA)
+    ref[5] = 0.0
+    np.testing.assert_allclose(F, ref, rtol=0, atol=1e-14 * (np.abs(ref).max() + 1))
+
+
+@pytest.mark.parametrize("riemann", ["hll", "hlld"])
+def test_direction_frames_are_cyclic_permutations(riemann):
+    """The y and z solvers are the x solver in the cyclic frames: cyclically
+    permuting the vector components of the states permutes the fluxes."""
+    rng = np.random.default_rng(5)
+    s = W.make_setup("t", 3, (4, 4, 4), gamma=GAMMA, cfl=0.3, riemann=riemann)
+    o = C.Oracle(s)
+    for _ in range(50):
+        VL, VR = random_state(rng), random_state(rng)
+        ch = rng.uniform(0.5, 3.0)
+        Fx = C.face_flux(o, 0, VL, VR, ch)
+        for d in [1, 2]:
+            perm = lambda V: np.array([V[0]] + [V[1 + (a - d) % 3] for a in range(3)] + [V[4]]
+                                      + [V[5 + (a - d) % 3] for a in range(3)] + [V[8]])
+            Fd = C.face_flux(o, d, perm(VL), perm(VR), ch)
+            np.testing.assert_array_equal(Fd, perm(Fx))
+
+
+def test_hlld_star_states_satisfy_jump_conditions():
+    """Across the outer waves S_L, S_R the single-star states obey the
+    Rankine-Hugoniot conditions with a total pressure p_T* and normal
+    velocity S_M shared by both sides (the HLLD assumptions): momentum,
+    tangential momentum, tangential field and energy fluxes of
+    F*_a = F_a + S_a (U*_a - U_a) equal their physical form in the star
+    state.  The outer speeds are the Davis bounds of the pinned fast speed."""
+    rng = np.random.default_rng(6)
+    for qL, qR in _fan_cases(rng, 200):
+        f = C.hlld_fan(qL, qR, GAMMA)
+        sL, _, sM, _, sR = f["s"]
+        cf = [C.fast_speed(np.r_[q[0], q[1:4], q[4], q[5:8], 0.0], GAMMA, 0) for q in (qL, qR)]
+        assert sL == min(qL[1] - cf[0], qR[1] - cf[1])
+        assert sR == max(qL[1] + cf[0], qR[1] + cf[1])
+        bn = qL[5]
+        pts = []
+        for s_out, U, F, Us in [(sL, f["UL"], f["FL"], f["UsL"]), (sR, f["UR"], f["FR"], f["UsR"])]:
+            Fs = F + s_out * (Us - U)
+            rho = Us[0]
+            assert Us[1] == pytest.approx(rho * sM, rel=1e-14)
+            vt, bt = Us[2:4] / rho, Us[6:8]
+            pt = Fs[1] - rho * sM * sM + bn * bn
+            pts.append(pt)
+            scale = np.abs(Fs).max() + 1.0
+            np.testing.assert_allclose(Fs[2:4], rho * sM * vt - bn * bt, atol=1e-13 * scale, rtol=0)
+            np.testing.assert_allclose(Fs[6:8], sM * bt - bn * vt, atol=1e-13 * scale, rtol=0)
+            vb = sM * bn + vt @ bt
+            assert Fs[4] == pytest.approx((Us[4] + pt) * sM - bn * vb, abs=1e-13 * scale)
+        assert pts[0] == pytest.approx(pts[1], abs=1e-13 * (1 + abs(pts[0])))
