@@ -1,0 +1,209 @@
+"""Benchmark of the fused ideal-MHD step on one MI355X.
+
+Workload: 3D periodic decaying MHD turbulence on a 512^3 grid, FP32 state
+and arithmetic (FP64 CFL reduction and conservation sums), PLM minmod +
+HLLD + GLM, SSP-RK2, CFL 0.3; synthetic seeded initial fields.
+
+A timed step is one pass of the whole hot path: the CFL maxima of the
+previous step's output are read back (one 16-byte device-to-host copy and
+stream sync), the GLM decay factor is formed, and mhd_step runs both stage
+kernels with the fused ghost fill, reconstruction, Riemann fluxes, flux
+divergence, psi damping, CFL and FP64-sum reductions.  Inputs are resident
+in HBM before timing starts.
+
+Prints one JSON line with the throughput (Mcell-updates/s), the roofline
+of the dominant kernel (stage 2) from HIP events recorded on the library's
+stream, FP64 figures on the same workload, and the FP64 CPU oracle timed on
+a bounded sample of the workload as a baseline.
+"""
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+METRIC = "Mcell-updates/s + % HBM roofline (FP32 vs FP64), adjoint/forward time ratio"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2510_24175_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch measured with rocprofv3 counters, if the stored
+    measurement was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    ent = data.get(kernel_key)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_gpu(n, dtype, steps, warmup, quiet=False):
+    import torch
+
+    from paper_2510_24175_amd import workloads
+    from paper_2510_24175_amd.mhd import Context
+
+    setup, V = workloads.turbulence(n)
+    ctx = Context(setup, dtype)
+    Vd = torch.from_numpy(V).cuda()
+    del V
+    a = ctx.prim_to_cons(Vd)
+    del Vd
+    b = torch.empty_like(a)
+    ncell = n * n * n
+
+    def one_step(first):
+        nonlocal a, b
+        if first:
+            dt, ch = ctx.cfl_dt(a)
+        else:
+            dt, ch, _ = ctx.step_info()
+        ctx.step(a, b, dt, ch, ctx.damp(dt, ch))
+        a, b = b, a
+
+    first = True
+    for _ in range(warmup):
+        one_step(first)
+        first = False
+    torch.cuda.synchronize()
+    ctx.timing_start(steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step(first)
+        first = False
+    _, _, sums = ctx.step_info()  # includes the last step's completion
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nt, st1, st2, red = ctx.timing_stop()
+    s = 4 if dtype == "f32" else 8
+    res = {
+        "ms_per_step": 1e3 * wall / steps,
+        "mcells": ncell * steps / wall / 1e6,
+        "stage1_ms": st1 / nt,
+        "stage2_ms": st2 / nt,
+        "reduce_ms": red / nt,
+        "elem": s,
+        "ncell": ncell,
+        "sums": sums,
+    }
+    # algorithmic HBM traffic: stage 1 reads Un and writes U1 (18 s B/cell),
+    # stage 2 reads Un and U1 and writes U_next (27 s B/cell)
+    res["alg_bytes_step"] = 45 * s * ncell
+    res["alg_bytes_stage2"] = 27 * s * ncell
+    res["hbm_frac_step"] = res["alg_bytes_step"] / (wall / steps) / (HBM_PEAK_GBS * 1e9)
+    del a, b
+    ctx.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(n_sample=128, steps=3):
+    """FP64 CPU oracle on a bounded sample of the same workload: the
+    [0, n_sample)^3 corner of the 512^3 turbulence fields, stepped with the
+    same scheme (periodic wrap of the sample)."""
+    from oracle import coracle
+    from paper_2510_24175_amd import workloads
+
+    setup, V = workloads.turbulence(n_sample)  # same mode sums, sampled on a coarser box
+    o = coracle.Oracle(setup)
+    U = o.prim_to_cons(V)
+    dt, ch = o.cfl(U)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dt, ch = o.cfl(U)
+        U = o.step(U, dt, ch)
+    wall = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": n_sample ** 3 * steps / wall / 1e6,
+        "unit": "Mcell-updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"turbulence {n_sample}^3 (same generator, FP64, PLM minmod + HLLD + GLM), "
+                  f"{steps} full RK2 steps incl. CFL, {wall:.1f} s wall",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    r32 = run_gpu(args.n, "f32", args.steps, args.warmup)
+    print(f"# f32 {args.n}^3: {r32['ms_per_step']:.3f} ms/step, stage1 {r32['stage1_ms']:.3f} ms, "
+          f"stage2 {r32['stage2_ms']:.3f} ms, reduce {r32['reduce_ms']:.3f} ms", file=sys.stderr,
+          flush=True)
+    out = {
+        "metric": METRIC,
+        "value": round(r32["mcells"], 2),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3D periodic decaying MHD turbulence {args.n}^3, FP32 state, FP64 CFL and sums, "
+                        "PLM minmod + HLLD + GLM, SSP-RK2, CFL 0.3",
+            "n": [args.n] * 3,
+            "parallelism": "single GPU",
+        },
+    }
+    ach = r32["alg_bytes_stage2"] / (r32["stage2_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(f"stage2_turbulence{args.n}_f32")
+    out["roofline"] = {
+        "bound": "hbm",
+        "kernel": "stage_kernel<float, HLLD, 3D, stage 2>",
+        "achieved": round(ach, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(ach / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "avg_launch_ms": round(r32["stage2_ms"], 4),
+    }
+    out["hbm_frac_step_algorithmic"] = round(r32["hbm_frac_step"], 4)
+    out["stage_ms"] = {"stage1": round(r32["stage1_ms"], 4), "stage2": round(r32["stage2_ms"], 4),
+                       "final_reduce": round(r32["reduce_ms"], 4)}
+    if not args.no_fp64:
+        r64 = run_gpu(args.n, "f64", max(3, args.steps // 2), 2)
+        out["fp64"] = {
+            "value": round(r64["mcells"], 2),
+            "ms_per_step": round(r64["ms_per_step"], 4),
+            "hbm_frac_step_algorithmic": round(r64["hbm_frac_step"], 4),
+            "stage2_ms": round(r64["stage2_ms"], 4),
+        }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

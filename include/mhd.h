@@ -1,0 +1,171 @@
+/*
+ * mhd.h - C ABI of the MI355X (gfx950) ideal-MHD finite-volume step.
+ *
+ * One call of mhd_step advances the conserved state
+ *     U = (rho, m_x, m_y, m_z, E, B_x, B_y, B_z, psi)
+ * on a uniform Cartesian grid by one second-order Runge-Kutta step of a
+ * Godunov-type finite-volume scheme.  The paper (section "Porting of
+ * gPLUTO") lists the steps repeated in every Runge-Kutta stage: boundary
+ * (ghost-zone) calculation, conservative -> primitive map, reconstruction of
+ * interface values, Riemann fluxes, right-hand side; plus one
+ * divergence-control algorithm, here GLM divergence cleaning (section
+ * "Results for gPLUTO", strong-scaling runs).  The paper prints no
+ * formulas; the operations follow the published methods it names or uses:
+ *   - ghosts: 2 layers per active face, periodic or zero-gradient outflow;
+ *   - reconstruction: piecewise linear in the primitive variables,
+ *     component-wise, minmod or MC limited (van Leer 1979);
+ *   - GLM: Dedner et al. (2002) mixed GLM, exact (B_n, psi) interface
+ *     solve, psi damped by exp(-alpha c_h dt / dh_min) once per step;
+ *   - Riemann: HLL (Harten, Lax & van Leer 1983) or HLLD (Miyoshi & Kusano
+ *     2005) with Davis wave-speed bounds;
+ *   - time: SSP-RK2 (Shu & Osher 1988), dt and c_h fixed for the step;
+ *   - CFL: dt = C / max_{cells,d} (|v_d| + c_f,d)/dx_d and
+ *     c_h = max_{cells,d} (|v_d| + c_f,d), reduced in FP64.
+ * Magnetic pressure is |B|^2/2; ideal gas E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2
+ * (psi is not part of E).  No density or pressure floors: a non-physical
+ * state is reported as MHD_ERR_NONPHYSICAL.
+ *
+ * Layout: every state array is one contiguous device buffer of shape
+ * [9][nz][ny][nx] (x fastest), interior cells only, element type of the
+ * context (float for MHD_F32, double for MHD_F64), at least 16-byte
+ * aligned.  Adjoint arrays (lambda) are always double with the same shape.
+ * Inactive dimensions have n = 1.
+ *
+ * Ownership: the caller owns every state, adjoint and primitive buffer.
+ * The library owns the context and its scratch (stage-1 buffer when the
+ * caller passes none, reduction partials, result and error words), all
+ * allocated by mhd_init and freed by mhd_destroy; mhd_step,
+ * mhd_step_adjoint and mhd_cfl_dt allocate nothing.
+ *
+ * Streams: all device work is enqueued on the context's HIP stream.  Calls
+ * marked "async" return without waiting; calls marked "syncs" wait for the
+ * stream.  Calls on one context must not overlap from several host
+ * threads.
+ *
+ * Errors: every call returns an mhd_status.  Arguments are validated before
+ * any device work is enqueued; on MHD_ERR_ARG nothing was enqueued.  HIP
+ * failures give MHD_ERR_HIP with the text in mhd_last_error.  Kernels raise
+ * a device flag on any cell with rho <= 0, p <= 0 or a non-finite value;
+ * the next syncing call returns MHD_ERR_NONPHYSICAL and clears the flag.
+ */
+#ifndef MHD_H
+#define MHD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mhd_ctx mhd_ctx; /* opaque */
+
+typedef enum {
+    MHD_OK = 0,
+    MHD_ERR_ARG = -1,         /* invalid argument; nothing enqueued           */
+    MHD_ERR_NO_DEVICE = -2,   /* no usable gfx950 device                      */
+    MHD_ERR_HIP = -3,         /* a HIP runtime call failed                    */
+    MHD_ERR_NONPHYSICAL = -4, /* rho <= 0, p <= 0 or non-finite state seen    */
+    MHD_ERR_UNSUPPORTED = -5  /* valid but not implemented combination        */
+} mhd_status;
+
+enum { MHD_F32 = 0, MHD_F64 = 1 };       /* storage and bulk arithmetic */
+enum { MHD_HLL = 0, MHD_HLLD = 1 };      /* Riemann solver              */
+enum { MHD_MINMOD = 0, MHD_MC = 1 };     /* slope limiter               */
+enum { MHD_PERIODIC = 0, MHD_OUTFLOW = 1 }; /* boundary per face        */
+
+typedef struct {
+    int32_t ndim;      /* 1, 2 or 3; axes >= ndim must have n = 1            */
+    int32_t dtype;     /* MHD_F32 or MHD_F64                                 */
+    int32_t riemann;   /* MHD_HLL or MHD_HLLD                                */
+    int32_t limiter;   /* MHD_MINMOD or MHD_MC                               */
+    int64_t n[3];      /* interior cells nx, ny, nz; n >= 2 on active axes   */
+    double lo[3];      /* domain lower corner                                */
+    double hi[3];      /* domain upper corner; dx_d = (hi-lo)/n              */
+    int32_t bc[3][2];  /* per axis, low and high face; periodic on both or none */
+    int32_t glm;       /* 1: GLM cleaning on; 0: psi inert, B_n = (B_L+B_R)/2 */
+    int32_t reserved;  /* must be 0                                          */
+    double gamma;      /* adiabatic index > 1                                */
+    double cfl;        /* Courant number C in (0, 1]                         */
+    double glm_alpha;  /* GLM damping parameter alpha >= 0                   */
+} mhd_config;
+
+/* Create a context for one grid on the current HIP device.  hip_stream is a
+ * hipStream_t (NULL = the null stream).  Allocates the library scratch.
+ * Returns MHD_ERR_ARG for an invalid config (bad ndim, n, bounds, dtype,
+ * solver, limiter, mixed periodic/outflow on one axis, gamma <= 1, cfl not
+ * in (0,1], glm_alpha < 0), MHD_ERR_NO_DEVICE when no gfx950 device is
+ * current.  *out is NULL on failure. */
+mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out);
+
+/* Release the context and its scratch (syncs).  NULL is ignored. */
+void mhd_destroy(mhd_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+mhd_status mhd_set_stream(mhd_ctx *ctx, void *hip_stream);
+
+/* Primitive -> conserved map (async).  V: device double [9][nz][ny][nx]
+ * holding (rho, vx, vy, vz, p, Bx, By, Bz, psi); U: device state of the
+ * context dtype.  E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2, computed in FP64
+ * and rounded once to the state type. */
+mhd_status mhd_prim_to_cons(mhd_ctx *ctx, const double *V, void *U);
+
+/* CFL reduction of a state (syncs): out[0] = C / max (|v_d|+c_f,d)/dx_d
+ * (not clipped to any end time), out[1] = c_h = max (|v_d|+c_f,d).  Each
+ * cell's state is converted to FP64 before the speeds are formed.  Returns
+ * MHD_ERR_NONPHYSICAL if any cell is non-physical. */
+mhd_status mhd_cfl_dt(mhd_ctx *ctx, const void *U, double out[2]);
+
+/* One SSP-RK2 step (async):
+ *   U1     = Un + dt L(Un)
+ *   U_next = (Un + U1 + dt L(U1)) / 2,  then psi <- psi * damp
+ * with L the flux divergence built with the given c_h.  U_next must not
+ * alias Un.  U1_out (may be NULL) receives the stage-1 state, which the
+ * adjoint reuses; otherwise library scratch is used.  The step also
+ * reduces, on U_next, the CFL maxima and the FP64 sums read back by
+ * mhd_step_info.  dt > 0, c_h > 0 when GLM is on, 0 < damp <= 1. */
+mhd_status mhd_step(mhd_ctx *ctx, const void *Un, void *U_next, void *U1_out, double dt,
+                    double c_h, double damp);
+
+/* Reductions of the last mhd_step output (syncs):
+ *   out[0] = C / max (|v_d|+c_f,d)/dx_d, out[1] = c_h (as mhd_cfl_dt),
+ *   out[2..10] = FP64 sums over cells of U_q times the cell volume.
+ * MHD_ERR_ARG if no step has run; MHD_ERR_NONPHYSICAL if a kernel saw a
+ * non-physical cell since the last syncing call. */
+mhd_status mhd_step_info(mhd_ctx *ctx, double out[11]);
+
+/* Adjoint of mhd_step (async): given lam_next = dJ/dU_next (double), write
+ * lam_n = dJ/dUn (double) for the same dt, c_h, damp, which are treated as
+ * constants (not differentiated).  U1 is the stage-1 state of that step
+ * (from mhd_step's U1_out) or NULL to recompute it.  lam_n must not alias
+ * lam_next.  Kinks (limiter switches, Riemann fan regions) take the branch
+ * the forward step took; at a tie |a| = |b| the minmod derivative follows
+ * the left difference. */
+mhd_status mhd_step_adjoint(mhd_ctx *ctx, const void *Un, const void *U1, const double *lam_next,
+                            double *lam_n, double dt, double c_h, double damp);
+
+/* Adjoint of mhd_prim_to_cons (async): lam_V = (dU/dV)^T lam_U, all double,
+ * V the primitive state the forward map was applied to. */
+mhd_status mhd_prim_to_cons_adjoint(mhd_ctx *ctx, const double *V, const double *lam_U,
+                                    double *lam_V);
+
+/* Kernel timing with HIP events on the context stream.  mhd_timing_start
+ * creates 4 events per step for up to `capacity` later mhd_step calls
+ * (the only allocation, made here) and starts recording; each mhd_step
+ * then records an event before its stage-1 kernel, between the two stage
+ * kernels, after stage 2 and after the final reduction.  mhd_timing_stop
+ * (syncs) returns out[0] = steps recorded, out[1..3] = total milliseconds
+ * of the stage-1 kernel, the stage-2 kernel and the final reduction over
+ * those steps, then frees the events.  Steps beyond capacity are not timed. */
+mhd_status mhd_timing_start(mhd_ctx *ctx, int32_t capacity);
+mhd_status mhd_timing_stop(mhd_ctx *ctx, double out[4]);
+
+const char *mhd_status_string(mhd_status st);
+
+/* Text of the last error on this context (never NULL). */
+const char *mhd_last_error(const mhd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHD_H */

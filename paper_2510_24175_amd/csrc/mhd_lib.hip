@@ -1,0 +1,472 @@
+// Host side of the C ABI declared in include/mhd.h: argument validation,
+// context and scratch management, kernel dispatch on the context stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mhd.h"
+#include "mhd_reduce.hpp"
+#include "mhd_stage.hpp"
+
+using namespace mhd;
+
+struct mhd_ctx {
+    mhd_config cfg;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    long long n[3] = {1, 1, 1};
+    long long ncell = 0;
+    size_t elem = 4;             // bytes per state element
+    void *u1_scratch = nullptr;  // stage-1 state when the caller passes none
+    double *part = nullptr;      // NPART x part_cap block partials
+    int part_cap = 0;
+    double *result = nullptr;    // device NPART doubles
+    int *flag = nullptr;         // device non-physical flag
+    double *host_res = nullptr;  // pinned NPART doubles + flag word
+    bool have_step = false;
+    double cell_volume = 1.0;
+    double dx[3] = {1, 1, 1};
+    std::vector<hipEvent_t> events; // 4 per timed step
+    int timed_cap = 0, timed_steps = 0;
+    std::string err;
+};
+
+namespace {
+
+constexpr int CFL_MAX_BLOCKS = 4096;
+
+mhd_status fail(mhd_ctx *ctx, mhd_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+#define HIP_TRY(ctx, call)                                                                     \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((ctx), MHD_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// Stage tile rows per workgroup for a state type and dimensionality.
+template <typename T, int NDIM> constexpr int tile_rows()
+{
+    return NDIM == 1 ? 1 : (sizeof(T) == 4 ? 8 : 4);
+}
+
+struct Launch {
+    int tiles_x, tiles_y, chunks, kz, nblocks;
+};
+
+Launch plan_stage(const mhd_ctx *ctx, int ty)
+{
+    Launch L;
+    L.tiles_x = (int)((ctx->n[0] + TX - 1) / TX);
+    L.tiles_y = (int)((ctx->n[1] + ty - 1) / ty);
+    const long long tiles = (long long)L.tiles_x * L.tiles_y;
+    int kz = 1;
+    if (ctx->cfg.ndim == 3) {
+        // long z chunks amortise the 4-plane warm-up; shorter chunks when
+        // the grid would otherwise leave compute units idle
+        kz = 64;
+        while (kz > 4 && tiles * ((ctx->n[2] + kz - 1) / kz) < 2048) kz >>= 1;
+    }
+    L.kz = kz;
+    L.chunks = (int)((ctx->n[2] + kz - 1) / kz);
+    L.nblocks = (int)(tiles * L.chunks);
+    return L;
+}
+
+template <typename T> Phys<T> make_phys(const mhd_ctx *ctx, double ch)
+{
+    Phys<T> p;
+    const double g = ctx->cfg.gamma;
+    p.gamma = (T)g;
+    p.gm1 = (T)(g - 1.0);
+    p.inv_gm1 = (T)(1.0 / (g - 1.0));
+    p.glm = ctx->cfg.glm ? 1 : 0;
+    p.ch = (T)(p.glm ? ch : 0.0);
+    p.ch2 = (T)(p.glm ? ch * ch : 0.0);
+    p.half_ich = (T)(p.glm ? 0.5 / ch : 0.0);
+    p.limiter = ctx->cfg.limiter;
+    return p;
+}
+
+template <typename T, int SOLVER, int NDIM>
+mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, double ch, double damp)
+{
+    constexpr int TY = tile_rows<T, NDIM>();
+    const Launch L = plan_stage(ctx, TY);
+    if (L.nblocks > ctx->part_cap) return fail(ctx, MHD_ERR_ARG, "grid too large for partials buffer");
+    StageArgs<T> a;
+    a.part = ctx->part;
+    a.flag = ctx->flag;
+    a.nx = (int)ctx->n[0];
+    a.ny = (int)ctx->n[1];
+    a.nz = (int)ctx->n[2];
+    a.nxy = ctx->n[0] * ctx->n[1];
+    a.ncell = ctx->ncell;
+    for (int d = 0; d < 3; ++d) {
+        a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
+        a.idx[d] = (T)(1.0 / ctx->dx[d]);
+        a.idx_d[d] = 1.0 / ctx->dx[d];
+    }
+    a.kz = L.kz;
+    a.tiles_x = L.tiles_x;
+    a.tiles_y = L.tiles_y;
+    a.chunks = L.chunks;
+    a.nblocks = L.nblocks;
+    a.dt = (T)dt;
+    a.damp = (T)damp;
+    a.gamma_d = ctx->cfg.gamma;
+    a.ph = make_phys<T>(ctx, ch);
+
+    hipEvent_t *ev = nullptr;
+    if (ctx->timed_steps < ctx->timed_cap) ev = &ctx->events[4 * ctx->timed_steps++];
+    if (ev) HIP_TRY(ctx, hipEventRecord(ev[0], ctx->stream));
+    a.uin = un;
+    a.un = un;
+    a.uout = u1;
+    hipLaunchKernelGGL((stage_kernel<T, SOLVER, NDIM, 1, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+                       ctx->stream, a);
+    HIP_TRY(ctx, hipGetLastError());
+    if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
+    a.uin = u1;
+    a.un = un;
+    a.uout = unext;
+    hipLaunchKernelGGL((stage_kernel<T, SOLVER, NDIM, 2, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+                       ctx->stream, a);
+    HIP_TRY(ctx, hipGetLastError());
+    if (ev) HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
+    hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(RED_THREADS), 0, ctx->stream,
+                       (const double *)ctx->part, L.nblocks, ctx->result);
+    HIP_TRY(ctx, hipGetLastError());
+    if (ev) HIP_TRY(ctx, hipEventRecord(ev[3], ctx->stream));
+    return MHD_OK;
+}
+
+template <typename T, int SOLVER>
+mhd_status launch_step_nd(mhd_ctx *ctx, const void *un, void *unext, void *u1, double dt, double ch,
+                          double damp)
+{
+    const T *a = (const T *)un;
+    T *b = (T *)unext, *c = (T *)u1;
+    switch (ctx->cfg.ndim) {
+    case 1: return launch_step<T, SOLVER, 1>(ctx, a, b, c, dt, ch, damp);
+    case 2: return launch_step<T, SOLVER, 2>(ctx, a, b, c, dt, ch, damp);
+    default: return launch_step<T, SOLVER, 3>(ctx, a, b, c, dt, ch, damp);
+    }
+}
+
+template <typename T>
+mhd_status launch_cfl(mhd_ctx *ctx, const T *U)
+{
+    const int nb = (int)std::min<long long>((ctx->ncell + RED_THREADS - 1) / RED_THREADS, CFL_MAX_BLOCKS);
+    const double i0 = 1.0 / ctx->dx[0], i1 = 1.0 / ctx->dx[1], i2 = 1.0 / ctx->dx[2];
+    switch (ctx->cfg.ndim) {
+    case 1:
+        hipLaunchKernelGGL((cfl_kernel<T, 1>), dim3(nb), dim3(RED_THREADS), 0, ctx->stream, U,
+                           ctx->ncell, ctx->cfg.gamma, i0, i1, i2, ctx->part, nb, ctx->flag);
+        break;
+    case 2:
+        hipLaunchKernelGGL((cfl_kernel<T, 2>), dim3(nb), dim3(RED_THREADS), 0, ctx->stream, U,
+                           ctx->ncell, ctx->cfg.gamma, i0, i1, i2, ctx->part, nb, ctx->flag);
+        break;
+    default:
+        hipLaunchKernelGGL((cfl_kernel<T, 3>), dim3(nb), dim3(RED_THREADS), 0, ctx->stream, U,
+                           ctx->ncell, ctx->cfg.gamma, i0, i1, i2, ctx->part, nb, ctx->flag);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(RED_THREADS), 0, ctx->stream,
+                       (const double *)ctx->part, nb, ctx->result);
+    HIP_TRY(ctx, hipGetLastError());
+    return MHD_OK;
+}
+
+// Copy the result words back, wait, and report (and clear) the flag.
+mhd_status sync_results(mhd_ctx *ctx)
+{
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_res, ctx->result, NPART * sizeof(double),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_res + NPART, ctx->flag, sizeof(int), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    int flag;
+    std::memcpy(&flag, ctx->host_res + NPART, sizeof(int));
+    if (flag) {
+        HIP_TRY(ctx, hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        return fail(ctx, MHD_ERR_NONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or non-finite)");
+    }
+    return MHD_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+mhd_status check_config(const mhd_config *c, std::string &why)
+{
+    if (!c) return why = "config is NULL", MHD_ERR_ARG;
+    if (c->ndim < 1 || c->ndim > 3) return why = "ndim must be 1, 2 or 3", MHD_ERR_ARG;
+    if (c->dtype != MHD_F32 && c->dtype != MHD_F64) return why = "bad dtype", MHD_ERR_ARG;
+    if (c->riemann != MHD_HLL && c->riemann != MHD_HLLD) return why = "bad riemann", MHD_ERR_ARG;
+    if (c->limiter != MHD_MINMOD && c->limiter != MHD_MC) return why = "bad limiter", MHD_ERR_ARG;
+    if (c->glm != 0 && c->glm != 1) return why = "glm must be 0 or 1", MHD_ERR_ARG;
+    if (c->reserved != 0) return why = "reserved must be 0", MHD_ERR_ARG;
+    long long cells = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (d < c->ndim) {
+            if (c->n[d] < 2) return why = "active axes need n >= 2", MHD_ERR_ARG;
+            if (!(c->hi[d] > c->lo[d]) || !std::isfinite(c->hi[d] - c->lo[d]))
+                return why = "hi must exceed lo on active axes", MHD_ERR_ARG;
+            for (int s = 0; s < 2; ++s)
+                if (c->bc[d][s] != MHD_PERIODIC && c->bc[d][s] != MHD_OUTFLOW)
+                    return why = "bad boundary kind", MHD_ERR_ARG;
+            if ((c->bc[d][0] == MHD_PERIODIC) != (c->bc[d][1] == MHD_PERIODIC))
+                return why = "periodic must apply to both faces of an axis", MHD_ERR_ARG;
+        } else if (c->n[d] != 1) {
+            return why = "inactive axes need n = 1", MHD_ERR_ARG;
+        }
+        if (c->n[d] > (1LL << 30)) return why = "axis too long", MHD_ERR_ARG;
+        cells *= c->n[d];
+    }
+    if (cells > (1LL << 40)) return why = "grid too large", MHD_ERR_ARG;
+    if (!(c->gamma > 1.0) || !std::isfinite(c->gamma)) return why = "gamma must exceed 1", MHD_ERR_ARG;
+    if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return why = "cfl must be in (0, 1]", MHD_ERR_ARG;
+    if (!(c->glm_alpha >= 0.0) || !std::isfinite(c->glm_alpha))
+        return why = "glm_alpha must be >= 0", MHD_ERR_ARG;
+    return MHD_OK;
+}
+
+void destroy_events(mhd_ctx *ctx)
+{
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    ctx->events.clear();
+    ctx->timed_cap = ctx->timed_steps = 0;
+}
+
+void free_ctx(mhd_ctx *ctx)
+{
+    destroy_events(ctx);
+    if (ctx->u1_scratch) (void)hipFree(ctx->u1_scratch);
+    if (ctx->part) (void)hipFree(ctx->part);
+    if (ctx->result) (void)hipFree(ctx->result);
+    if (ctx->flag) (void)hipFree(ctx->flag);
+    if (ctx->host_res) (void)hipHostFree(ctx->host_res);
+    delete ctx;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *mhd_status_string(mhd_status st)
+{
+    switch (st) {
+    case MHD_OK: return "ok";
+    case MHD_ERR_ARG: return "invalid argument";
+    case MHD_ERR_NO_DEVICE: return "no usable gfx950 device";
+    case MHD_ERR_HIP: return "HIP runtime error";
+    case MHD_ERR_NONPHYSICAL: return "non-physical state";
+    case MHD_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+mhd_status mhd_timing_start(mhd_ctx *ctx, int32_t capacity)
+{
+    if (!ctx) return MHD_ERR_ARG;
+    if (capacity < 1 || capacity > (1 << 20)) return fail(ctx, MHD_ERR_ARG, "capacity out of range");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    destroy_events(ctx);
+    ctx->events.resize(4 * (size_t)capacity, nullptr);
+    for (auto &e : ctx->events) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            e = nullptr;
+            destroy_events(ctx);
+            return fail(ctx, MHD_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(r));
+        }
+    }
+    ctx->timed_cap = capacity;
+    ctx->timed_steps = 0;
+    return MHD_OK;
+}
+
+mhd_status mhd_timing_stop(mhd_ctx *ctx, double out[4])
+{
+    if (!ctx) return MHD_ERR_ARG;
+    if (!out) return fail(ctx, MHD_ERR_ARG, "null buffer");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    out[0] = ctx->timed_steps;
+    out[1] = out[2] = out[3] = 0.0;
+    for (int s = 0; s < ctx->timed_steps; ++s) {
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->events[4 * s + k], ctx->events[4 * s + k + 1]));
+            out[1 + k] += ms;
+        }
+    }
+    destroy_events(ctx);
+    return MHD_OK;
+}
+
+const char *mhd_last_error(const mhd_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
+{
+    if (!out) return MHD_ERR_ARG;
+    *out = nullptr;
+    std::string why;
+    if (check_config(cfg, why) != MHD_OK) return MHD_ERR_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MHD_ERR_NO_DEVICE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MHD_ERR_NO_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MHD_ERR_NO_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MHD_ERR_NO_DEVICE;
+
+    mhd_ctx *ctx = new (std::nothrow) mhd_ctx();
+    if (!ctx) return MHD_ERR_HIP;
+    ctx->cfg = *cfg;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->device = dev;
+    ctx->ncell = 1;
+    ctx->cell_volume = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        ctx->n[d] = cfg->n[d];
+        ctx->ncell *= cfg->n[d];
+        ctx->dx[d] = d < cfg->ndim ? (cfg->hi[d] - cfg->lo[d]) / (double)cfg->n[d] : 1.0;
+        if (d < cfg->ndim) ctx->cell_volume *= ctx->dx[d];
+    }
+    ctx->elem = cfg->dtype == MHD_F32 ? 4 : 8;
+    const int ty = cfg->ndim == 1 ? 1 : (cfg->dtype == MHD_F32 ? 8 : 4);
+    const Launch L = plan_stage(ctx, ty);
+    ctx->part_cap = std::max(L.nblocks, CFL_MAX_BLOCKS);
+    hipError_t e = hipMalloc(&ctx->u1_scratch, (size_t)NQ * ctx->ncell * ctx->elem);
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->part, (size_t)NPART * ctx->part_cap * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->result, NPART * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->flag, sizeof(int));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->host_res, (NPART + 1) * sizeof(double));
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        free_ctx(ctx);
+        return MHD_ERR_HIP;
+    }
+    *out = ctx;
+    return MHD_OK;
+}
+
+void mhd_destroy(mhd_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_ctx(ctx);
+}
+
+mhd_status mhd_set_stream(mhd_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return MHD_ERR_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return MHD_OK;
+}
+
+mhd_status mhd_prim_to_cons(mhd_ctx *ctx, const double *V, void *U)
+{
+    if (!ctx) return MHD_ERR_ARG;
+    if (!V || !U) return fail(ctx, MHD_ERR_ARG, "null buffer");
+    const int nb = (int)std::min<long long>((ctx->ncell + RED_THREADS - 1) / RED_THREADS, 8192);
+    const double ig = 1.0 / (ctx->cfg.gamma - 1.0);
+    if (ctx->cfg.dtype == MHD_F32)
+        hipLaunchKernelGGL(prim_to_cons_kernel<float>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, V,
+                           (float *)U, ctx->ncell, ig);
+    else
+        hipLaunchKernelGGL(prim_to_cons_kernel<double>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, V,
+                           (double *)U, ctx->ncell, ig);
+    HIP_TRY(ctx, hipGetLastError());
+    return MHD_OK;
+}
+
+mhd_status mhd_prim_to_cons_adjoint(mhd_ctx *ctx, const double *V, const double *lam_U, double *lam_V)
+{
+    if (!ctx) return MHD_ERR_ARG;
+    if (!V || !lam_U || !lam_V) return fail(ctx, MHD_ERR_ARG, "null buffer");
+    if (lam_U == lam_V) return fail(ctx, MHD_ERR_ARG, "lam_V must not alias lam_U");
+    const int nb = (int)std::min<long long>((ctx->ncell + RED_THREADS - 1) / RED_THREADS, 8192);
+    hipLaunchKernelGGL(prim_to_cons_adjoint_kernel, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, V,
+                       lam_U, lam_V, ctx->ncell, 1.0 / (ctx->cfg.gamma - 1.0));
+    HIP_TRY(ctx, hipGetLastError());
+    return MHD_OK;
+}
+
+mhd_status mhd_cfl_dt(mhd_ctx *ctx, const void *U, double out[2])
+{
+    if (!ctx) return MHD_ERR_ARG;
+    if (!U || !out) return fail(ctx, MHD_ERR_ARG, "null buffer");
+    mhd_status st = ctx->cfg.dtype == MHD_F32 ? launch_cfl<float>(ctx, (const float *)U)
+                                               : launch_cfl<double>(ctx, (const double *)U);
+    if (st != MHD_OK) return st;
+    st = sync_results(ctx);
+    if (st != MHD_OK) return st;
+    out[0] = ctx->cfg.cfl / ctx->host_res[0];
+    out[1] = ctx->host_res[1];
+    return MHD_OK;
+}
+
+mhd_status mhd_step(mhd_ctx *ctx, const void *Un, void *U_next, void *U1_out, double dt, double c_h,
+                    double damp)
+{
+    if (!ctx) return MHD_ERR_ARG;
+    if (!Un || !U_next) return fail(ctx, MHD_ERR_ARG, "null buffer");
+    if (Un == U_next || U1_out == Un || (U1_out && U1_out == U_next))
+        return fail(ctx, MHD_ERR_ARG, "state buffers must not alias");
+    if (!finite_pos(dt)) return fail(ctx, MHD_ERR_ARG, "dt must be finite and > 0");
+    if (ctx->cfg.glm && !finite_pos(c_h)) return fail(ctx, MHD_ERR_ARG, "c_h must be finite and > 0");
+    if (!(damp > 0.0 && damp <= 1.0)) return fail(ctx, MHD_ERR_ARG, "damp must be in (0, 1]");
+    void *u1 = U1_out ? U1_out : ctx->u1_scratch;
+    mhd_status st;
+    const bool f32 = ctx->cfg.dtype == MHD_F32;
+    if (ctx->cfg.riemann == MHD_HLLD)
+        st = f32 ? launch_step_nd<float, SOLVER_HLLD>(ctx, Un, U_next, u1, dt, c_h, damp)
+                 : launch_step_nd<double, SOLVER_HLLD>(ctx, Un, U_next, u1, dt, c_h, damp);
+    else
+        st = f32 ? launch_step_nd<float, SOLVER_HLL>(ctx, Un, U_next, u1, dt, c_h, damp)
+                 : launch_step_nd<double, SOLVER_HLL>(ctx, Un, U_next, u1, dt, c_h, damp);
+    if (st == MHD_OK) ctx->have_step = true;
+    return st;
+}
+
+mhd_status mhd_step_info(mhd_ctx *ctx, double out[11])
+{
+    if (!ctx) return MHD_ERR_ARG;
+    if (!out) return fail(ctx, MHD_ERR_ARG, "null buffer");
+    if (!ctx->have_step) return fail(ctx, MHD_ERR_ARG, "no step has run on this context");
+    mhd_status st = sync_results(ctx);
+    if (st != MHD_OK) return st;
+    out[0] = ctx->cfg.cfl / ctx->host_res[0];
+    out[1] = ctx->host_res[1];
+    for (int q = 0; q < NQ; ++q) out[2 + q] = ctx->host_res[2 + q] * ctx->cell_volume;
+    return MHD_OK;
+}
+
+mhd_status mhd_step_adjoint(mhd_ctx *ctx, const void *Un, const void *U1, const double *lam_next,
+                            double *lam_n, double dt, double c_h, double damp)
+{
+    if (!ctx) return MHD_ERR_ARG;
+    if (!Un || !lam_next || !lam_n) return fail(ctx, MHD_ERR_ARG, "null buffer");
+    if (lam_next == lam_n) return fail(ctx, MHD_ERR_ARG, "lam_n must not alias lam_next");
+    if (!finite_pos(dt)) return fail(ctx, MHD_ERR_ARG, "dt must be finite and > 0");
+    if (ctx->cfg.glm && !finite_pos(c_h)) return fail(ctx, MHD_ERR_ARG, "c_h must be finite and > 0");
+    if (!(damp > 0.0 && damp <= 1.0)) return fail(ctx, MHD_ERR_ARG, "damp must be in (0, 1]");
+    (void)U1;
+    return fail(ctx, MHD_ERR_UNSUPPORTED, "adjoint step not available yet");
+}
+
+} // extern "C"

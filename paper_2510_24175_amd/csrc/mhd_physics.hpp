@@ -1,0 +1,318 @@
+// Device-side pointwise physics of the ideal-MHD finite-volume step.
+//
+// Conventions (shared with include/mhd.h):
+//   primitive  V = (rho, vx, vy, vz, p, Bx, By, Bz, psi)
+//   conserved  U = (rho, mx, my, mz, E, Bx, By, Bz, psi)
+//   E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2   (magnetic pressure |B|^2/2)
+// A face normal to axis d is solved in the cyclic frame (n, t1, t2) =
+// (d, d+1, d+2) mod 3.  Everything is templated on the arithmetic type T
+// (float or double); reciprocals and square roots go through Num<T>, which
+// uses the hardware approximations in FP32 and IEEE operations in FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mhd {
+
+enum { NQ = 9 };
+enum { RHO = 0, VX = 1, VY = 2, VZ = 3, PRS = 4, BX = 5, BY = 6, BZ = 7, PSI = 8 };
+enum { MX = 1, MY = 2, MZ = 3, ENG = 4 };
+enum { SOLVER_HLL = 0, SOLVER_HLLD = 1 };
+enum { LIM_MINMOD = 0, LIM_MC = 1 };
+
+template <typename T> struct Num;
+
+template <> struct Num<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static constexpr float eps = 1.1920928955078125e-7f;
+};
+
+template <> struct Num<double> {
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double sqrt(double x) { return __builtin_sqrt(x); }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
+    static constexpr double eps = 2.220446049250313e-16;
+};
+
+// Per-launch constants of the scheme.
+template <typename T> struct Phys {
+    T gamma;     // adiabatic index
+    T gm1;       // gamma - 1
+    T inv_gm1;   // 1 / (gamma - 1)
+    T ch;        // GLM wave speed c_h
+    T ch2;       // c_h^2
+    T half_ich;  // 1 / (2 c_h), 0 when GLM is off
+    int glm;     // GLM cleaning on
+    int limiter; // LIM_MINMOD or LIM_MC
+};
+
+// Conserved -> primitive.  Returns false for rho <= 0, p <= 0 or a
+// non-finite value (NaN fails every comparison; infinities fail the upper
+// bounds or turn p into NaN or -inf).
+template <typename T>
+__device__ __forceinline__ bool cons_to_prim(const T *u, const Phys<T> &ph, T *v)
+{
+    const T rho = u[RHO];
+    const T ir = Num<T>::rcp(rho);
+    const T vx = u[MX] * ir, vy = u[MY] * ir, vz = u[MZ] * ir;
+    const T kin = T(0.5) * (u[MX] * vx + u[MY] * vy + u[MZ] * vz);
+    const T mag = T(0.5) * (u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ]);
+    const T p = ph.gm1 * (u[ENG] - kin - mag);
+    v[RHO] = rho;
+    v[VX] = vx;
+    v[VY] = vy;
+    v[VZ] = vz;
+    v[PRS] = p;
+    v[BX] = u[BX];
+    v[BY] = u[BY];
+    v[BZ] = u[BZ];
+    v[PSI] = u[PSI];
+    const T big = T(3.0e38);
+    return (rho > T(0)) & (rho < big) & (p > T(0)) & (p < big) & (__builtin_fabs(u[PSI]) < big);
+}
+
+// Limited slope from the backward difference a and the forward difference b:
+// minmod(a, b), or MC = minmod(2a, 2b, (a+b)/2).
+template <typename T> __device__ __forceinline__ T limited_slope(T a, T b, int limiter)
+{
+    T m = __builtin_fmin(__builtin_fabs(a), __builtin_fabs(b));
+    if (limiter == LIM_MC) m = __builtin_fmin(T(2) * m, T(0.5) * __builtin_fabs(a + b));
+    return (a * b > T(0)) ? __builtin_copysign(m, a) : T(0);
+}
+
+// Fast magnetosonic speed from rho, p, |B|^2 and B_n^2:
+// c_f^2 = (a^2 + b^2 + sqrt((a^2 - b^2)^2 + 4 a^2 (b^2 - b_n^2))) / 2.
+template <typename T>
+__device__ __forceinline__ T fast_speed(T rho, T p, T bsq, T bnsq, T gamma, T irho)
+{
+    const T a2 = gamma * p * irho;
+    const T b2 = bsq * irho;
+    const T bn2 = bnsq * irho;
+    const T dab = a2 - b2;
+    T disc = dab * dab + T(4) * a2 * (b2 - bn2);
+    disc = __builtin_fmax(disc, T(0));
+    return Num<T>::sqrt(T(0.5) * (a2 + b2 + Num<T>::sqrt(disc)));
+}
+
+// A rotated 8-component state: rho, u (normal), v1, v2, p, bn, b1, b2, with
+// its derived energy, total pressure and v.B.
+template <typename T> struct RState {
+    T rho, u, v1, v2, p, bn, b1, b2;
+    T irho, E, pt, vb;
+};
+
+template <typename T>
+__device__ __forceinline__ void rstate_finish(RState<T> &s, const Phys<T> &ph)
+{
+    s.irho = Num<T>::rcp(s.rho);
+    const T bsq = s.bn * s.bn + s.b1 * s.b1 + s.b2 * s.b2;
+    s.E = s.p * ph.inv_gm1 + T(0.5) * s.rho * (s.u * s.u + s.v1 * s.v1 + s.v2 * s.v2) +
+          T(0.5) * bsq;
+    s.pt = s.p + T(0.5) * bsq;
+    s.vb = s.u * s.bn + s.v1 * s.b1 + s.v2 * s.b2;
+}
+
+// physical normal flux (8 comps, slot 5 unused) and conserved vector
+template <typename T>
+__device__ __forceinline__ void rstate_flux(const RState<T> &s, T *f, T *c)
+{
+    const T mu = s.rho * s.u;
+    f[0] = mu;
+    f[1] = mu * s.u + s.pt - s.bn * s.bn;
+    f[2] = mu * s.v1 - s.bn * s.b1;
+    f[3] = mu * s.v2 - s.bn * s.b2;
+    f[4] = (s.E + s.pt) * s.u - s.bn * s.vb;
+    f[5] = T(0);
+    f[6] = s.u * s.b1 - s.v1 * s.bn;
+    f[7] = s.u * s.b2 - s.v2 * s.bn;
+    c[0] = s.rho;
+    c[1] = mu;
+    c[2] = s.rho * s.v1;
+    c[3] = s.rho * s.v2;
+    c[4] = s.E;
+    c[5] = s.bn;
+    c[6] = s.b1;
+    c[7] = s.b2;
+}
+
+template <typename T>
+__device__ __forceinline__ T rstate_fast(const RState<T> &s, const Phys<T> &ph)
+{
+    const T bsq = s.bn * s.bn + s.b1 * s.b1 + s.b2 * s.b2;
+    return fast_speed(s.rho, s.p, bsq, s.bn * s.bn, ph.gamma, s.irho);
+}
+
+// HLL flux, Davis bounds clamped to the origin so one formula covers the
+// supersonic cases: F = (sR FL - sL FR + sL sR (UR - UL)) / (sR - sL).
+template <typename T>
+__device__ __forceinline__ void hll_flux(const RState<T> &L, const RState<T> &R,
+                                         const Phys<T> &ph, T *F)
+{
+    T FL[8], UL[8], FR[8], UR[8];
+    rstate_flux(L, FL, UL);
+    rstate_flux(R, FR, UR);
+    const T cL = rstate_fast(L, ph), cR = rstate_fast(R, ph);
+    const T sL = __builtin_fmin(__builtin_fmin(L.u - cL, R.u - cR), T(0));
+    const T sR = __builtin_fmax(__builtin_fmax(L.u + cL, R.u + cR), T(0));
+    const T id = Num<T>::rcp(sR - sL);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) F[k] = (sR * FL[k] - sL * FR[k] + sL * sR * (UR[k] - UL[k])) * id;
+}
+
+// One side of the HLLD single-star state (Miyoshi & Kusano 2005).
+template <typename T> struct Star {
+    T rho, v1, v2, b1, b2, E, sq; // sq = sqrt(rho*)
+    T vb;                         // v* . B*
+};
+
+template <typename T>
+__device__ __forceinline__ void hlld_star(const RState<T> &s, T S, T sM, T pts, Star<T> &o)
+{
+    const T su = S - s.u;
+    const T isd = Num<T>::rcp(S - sM);
+    const T m = s.rho * su;
+    o.rho = m * isd;
+    const T mm = m * (S - sM);
+    const T bn2 = s.bn * s.bn;
+    const T D = mm - bn2;
+    const bool degenerate = __builtin_fabs(D) <= T(16) * Num<T>::eps * (__builtin_fabs(mm) + bn2);
+    const T iD = Num<T>::rcp(D);
+    const T cv = s.bn * (sM - s.u) * iD;
+    const T cb = (m * su - bn2) * iD;
+    o.v1 = degenerate ? s.v1 : s.v1 - s.b1 * cv;
+    o.v2 = degenerate ? s.v2 : s.v2 - s.b2 * cv;
+    o.b1 = degenerate ? s.b1 : s.b1 * cb;
+    o.b2 = degenerate ? s.b2 : s.b2 * cb;
+    o.vb = sM * s.bn + o.v1 * o.b1 + o.v2 * o.b2;
+    o.E = (su * s.E - s.pt * s.u + pts * sM + s.bn * (s.vb - o.vb)) * isd;
+    o.sq = Num<T>::sqrt(o.rho);
+}
+
+// HLLD flux (Miyoshi & Kusano 2005) with Davis outer speeds.
+template <typename T>
+__device__ __forceinline__ void hlld_flux(const RState<T> &L, const RState<T> &R,
+                                          const Phys<T> &ph, T *F)
+{
+    const T cL = rstate_fast(L, ph), cR = rstate_fast(R, ph);
+    const T sL = __builtin_fmin(L.u - cL, R.u - cR);
+    const T sR = __builtin_fmax(L.u + cL, R.u + cR);
+    const T mL = (sL - L.u) * L.rho, mR = (sR - R.u) * R.rho;
+    const T idm = Num<T>::rcp(mR - mL);
+    const T sM = (mR * R.u - mL * L.u - R.pt + L.pt) * idm;
+    const T pts = (mR * L.pt - mL * R.pt + mL * mR * (R.u - L.u)) * idm;
+    const T bn = L.bn;
+
+    Star<T> sl, sr;
+    hlld_star(L, sL, sM, pts, sl);
+    hlld_star(R, sR, sM, pts, sr);
+
+    const T sgn = bn >= T(0) ? T(1) : T(-1);
+    const T abn = __builtin_fabs(bn);
+    const T ssL = sM - abn * Num<T>::rcp(sl.sq);
+    const T ssR = sM + abn * Num<T>::rcp(sr.sq);
+    const T iden = Num<T>::rcp(sl.sq + sr.sq);
+    const T v1 = (sl.sq * sl.v1 + sr.sq * sr.v1 + (sr.b1 - sl.b1) * sgn) * iden;
+    const T v2 = (sl.sq * sl.v2 + sr.sq * sr.v2 + (sr.b2 - sl.b2) * sgn) * iden;
+    const T sqq = sl.sq * sr.sq;
+    const T b1 = (sl.sq * sr.b1 + sr.sq * sl.b1 + sqq * (sr.v1 - sl.v1) * sgn) * iden;
+    const T b2 = (sl.sq * sr.b2 + sr.sq * sl.b2 + sqq * (sr.v2 - sl.v2) * sgn) * iden;
+    const T vbss = sM * bn + v1 * b1 + v2 * b2;
+
+    // side of the contact and the region within it
+    const bool left = sM >= T(0);
+    const RState<T> &S = left ? L : R;
+    const Star<T> &st = left ? sl : sr;
+    const T s_out = left ? sL : sR;
+    const T s_in = left ? ssL : ssR;
+    // outer region: sL >= 0 (left) or sR <= 0 (right)
+    const bool outer = left ? (sL >= T(0)) : (sR <= T(0));
+    // double-star region: s*L < 0 (left of contact) or s*R >= 0 (right)
+    const bool dbl = left ? (ssL < T(0)) : (ssR >= T(0));
+    const T a1 = outer ? T(0) : s_out;
+    const T a2 = (outer || !dbl) ? T(0) : s_in;
+    const T Ess = st.E + (left ? -st.sq : st.sq) * (st.vb - vbss) * sgn;
+
+    T f[8], u[8];
+    rstate_flux(S, f, u);
+    const T us[8] = {st.rho, st.rho * sM, st.rho * st.v1, st.rho * st.v2, st.E, bn, st.b1, st.b2};
+    const T uss[8] = {st.rho, st.rho * sM, st.rho * v1, st.rho * v2, Ess, bn, b1, b2};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) F[k] = f[k] + a1 * (us[k] - u[k]) + a2 * (uss[k] - us[k]);
+}
+
+// Select a[d] for d in {0,1,2} without indexing a register array (the
+// selects fold away when d is a compile-time constant).
+template <typename T> __device__ __forceinline__ T pick3(int d, T a0, T a1, T a2)
+{
+    return d == 0 ? a0 : (d == 1 ? a1 : a2);
+}
+
+// Interface flux from two unrotated primitive face states along axis d:
+// GLM (B_n, psi) interface solve, MHD solver on the 8 MHD components with
+// B_n replaced by B_n*, then F(B_n) = psi*, F(psi) = c_h^2 B_n*.
+template <typename T, int SOLVER>
+__device__ __forceinline__ void face_flux(const T *VL, const T *VR, int d, const Phys<T> &ph, T *F)
+{
+    // frame (n, t1, t2) = (d, d+1, d+2) mod 3
+    const T bnL = pick3(d, VL[BX], VL[BY], VL[BZ]);
+    const T bnR = pick3(d, VR[BX], VR[BY], VR[BZ]);
+    T bns, psis;
+    if (ph.glm) {
+        bns = T(0.5) * (bnL + bnR) - (VR[PSI] - VL[PSI]) * ph.half_ich;
+        psis = T(0.5) * (VL[PSI] + VR[PSI]) - T(0.5) * ph.ch * (bnR - bnL);
+    } else {
+        bns = T(0.5) * (bnL + bnR);
+        psis = T(0);
+    }
+    RState<T> L, R;
+    L.rho = VL[RHO];
+    L.u = pick3(d, VL[VX], VL[VY], VL[VZ]);
+    L.v1 = pick3(d, VL[VY], VL[VZ], VL[VX]);
+    L.v2 = pick3(d, VL[VZ], VL[VX], VL[VY]);
+    L.p = VL[PRS];
+    L.bn = bns;
+    L.b1 = pick3(d, VL[BY], VL[BZ], VL[BX]);
+    L.b2 = pick3(d, VL[BZ], VL[BX], VL[BY]);
+    R.rho = VR[RHO];
+    R.u = pick3(d, VR[VX], VR[VY], VR[VZ]);
+    R.v1 = pick3(d, VR[VY], VR[VZ], VR[VX]);
+    R.v2 = pick3(d, VR[VZ], VR[VX], VR[VY]);
+    R.p = VR[PRS];
+    R.bn = bns;
+    R.b1 = pick3(d, VR[BY], VR[BZ], VR[BX]);
+    R.b2 = pick3(d, VR[BZ], VR[BX], VR[BY]);
+    rstate_finish(L, ph);
+    rstate_finish(R, ph);
+    T f[8];
+    if (SOLVER == SOLVER_HLLD)
+        hlld_flux(L, R, ph, f);
+    else
+        hll_flux(L, R, ph, f);
+    const T fbn = ph.glm ? psis : T(0);
+    F[RHO] = f[0];
+    F[ENG] = f[4];
+    // unrotate: component x is (n, t2, t1) for d = (0, 1, 2), etc.
+    F[MX] = pick3(d, f[1], f[3], f[2]);
+    F[MY] = pick3(d, f[2], f[1], f[3]);
+    F[MZ] = pick3(d, f[3], f[2], f[1]);
+    F[BX] = pick3(d, fbn, f[7], f[6]);
+    F[BY] = pick3(d, f[6], fbn, f[7]);
+    F[BZ] = pick3(d, f[7], f[6], fbn);
+    F[PSI] = ph.glm ? ph.ch2 * bns : T(0);
+}
+
+// Boundary index map of a ghost or interior coordinate m on an axis of n
+// cells: periodic wrap or zero-gradient clamp.  Valid for any m (values
+// beyond the two ghost layers are only ever used as padding).
+__device__ __forceinline__ int remap_index(int m, int n, int periodic)
+{
+    if (periodic) {
+        m %= n;
+        return m < 0 ? m + n : m;
+    }
+    return m < 0 ? 0 : (m >= n ? n - 1 : m);
+}
+
+} // namespace mhd

@@ -1,0 +1,349 @@
+// Fused Runge-Kutta stage kernel: ghost fill (index remap), conservative ->
+// primitive, PLM reconstruction, GLM + Riemann fluxes on every face, flux
+// divergence and the stage combine, in one pass over the grid.
+//
+// Work decomposition (gfx950, wave64):
+//   * a workgroup owns a tile of TX = 64 (x) by TY (y) columns and marches
+//     along z over a chunk of planes [k0, k1);
+//   * one wave per tile row, one lane per column; the primitive state of
+//     the current plane, with a 2-cell x/y halo, sits in LDS;
+//   * z-faces come from a per-lane register window (V(k), V(k+1) and the
+//     limited slope of V(k)) slid along the march, so every z-face flux is
+//     computed once per chunk plus one warm-up face;
+//   * x- and y-faces of the plane are a flat work list of
+//     TY(TX+1) + (TY+1)TX items spread over the workgroup; their fluxes
+//     go through LDS to the cells on both sides, so each face is solved
+//     once per tile;
+//   * ghost cells are never stored: out-of-range coordinates are mapped to
+//     interior cells by the boundary rule when addresses are formed.
+// Stage 1 writes U1 = Un + dt L(Un); stage 2 writes
+// U_next = (Un + U1 + dt L(U1)) / 2 with psi damped, and reduces on U_next
+// the CFL maxima (FP64) and the FP64 conservation sums into per-block
+// partials.
+#pragma once
+
+#include "mhd_physics.hpp"
+
+namespace mhd {
+
+constexpr int TX = 64;
+// partial layout: [NPART][nblocks]; 0: max (|v|+cf)/dx, 1: max (|v|+cf),
+// 2..10: sums of the 9 conserved components
+constexpr int NPART = 11;
+
+template <typename T> struct StageArgs {
+    const T *uin;   // state the fluxes are built from (Un or U1)
+    const T *un;    // Un (stage 2 combine); equals uin in stage 1
+    T *uout;        // U1 (stage 1) or U_next (stage 2)
+    double *part;   // stage 2: NPART x nblocks partials
+    int *flag;      // non-physical flag
+    int nx, ny, nz; // interior cells
+    long long nxy;  // nx*ny
+    long long ncell;
+    int per[3];     // periodic per axis
+    int kz;         // planes per chunk
+    int tiles_x, tiles_y, chunks;
+    int nblocks;
+    T dt;
+    T idx[3];       // 1/dx per axis
+    T damp;
+    double gamma_d; // FP64 copies for the reductions
+    double idx_d[3];
+    Phys<T> ph;
+};
+
+// Logical block id from the hardware id.  Consecutive hardware ids are
+// dispatched round-robin over the 8 XCDs; giving each XCD a contiguous
+// range of logical ids keeps neighbouring tiles (shared halos) in one L2.
+__device__ __forceinline__ int logical_block(int hw, int nblocks)
+{
+    if ((nblocks & 7) != 0) return hw;
+    return (hw & 7) * (nblocks >> 3) + (hw >> 3);
+}
+
+// FP64 signal speeds of one conserved cell state (any T), for the CFL
+// reduction: smax = max_d (|v_d| + c_f,d)/dx_d, cmax = max_d (|v_d| + c_f,d).
+template <typename T, int NDIM>
+__device__ __forceinline__ bool cell_speeds(const T *u, double gamma, const double *idx,
+                                            double &smax, double &cmax)
+{
+    const double rho = (double)u[RHO];
+    const double ir = 1.0 / rho;
+    const double m[3] = {(double)u[MX], (double)u[MY], (double)u[MZ]};
+    const double b[3] = {(double)u[BX], (double)u[BY], (double)u[BZ]};
+    const double bsq = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    const double kin = 0.5 * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * ir;
+    const double p = (gamma - 1.0) * ((double)u[ENG] - kin - 0.5 * bsq);
+    bool ok = (rho > 0.0) & (rho < 1e300) & (p > 0.0) & (p < 1e300);
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        const double lam = __builtin_fabs(m[d] * ir) + fast_speed(rho, p, bsq, b[d] * b[d], gamma, ir);
+        smax = __builtin_fmax(smax, lam * idx[d]);
+        cmax = __builtin_fmax(cmax, lam);
+    }
+    return ok;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_cell(const T *__restrict__ U, long long ncell, long long c, T *u)
+{
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) u[q] = U[q * ncell + c];
+}
+
+// Wave64 sum / max of a double.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = __builtin_fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <typename T, int SOLVER, int NDIM, int STAGE, int TY>
+__global__ void __launch_bounds__(TX *TY) stage_kernel(const StageArgs<T> a)
+{
+    constexpr int NT = TX * TY;
+    constexpr int HY = NDIM >= 2 ? 2 : 0;  // y halo width in LDS
+    constexpr int PX = TX + 4;             // LDS row pitch
+    constexpr int PY = TY + 2 * HY;        // LDS rows
+    constexpr int PLANE = PX * PY;         // LDS elements per component
+    constexpr int NFX = TY * (TX + 1);     // x-face items
+    constexpr int NFY = NDIM >= 2 ? (TY + 1) * TX : 0;
+    constexpr int NHX = 4 * TY;            // x-halo cells
+    constexpr int NH = NHX + (NDIM >= 2 ? 4 * TX : 0);
+
+    __shared__ T P[NQ * PLANE];
+    __shared__ T FXs[NQ * TY * (TX + 1)];
+    __shared__ T FYs[NDIM >= 2 ? NQ * (TY + 1) * TX : 1];
+
+    const int t = threadIdx.x;
+    const int tx = t & (TX - 1);
+    const int ty = t / TX;
+    const int lb = logical_block(blockIdx.x, a.nblocks);
+    const int tile_x = lb % a.tiles_x;
+    const int rest = lb / a.tiles_x;
+    const int tile_y = rest % a.tiles_y;
+    const int chunk = rest / a.tiles_y;
+    const int i0 = tile_x * TX, j0 = tile_y * TY;
+    const int k0 = chunk * a.kz;
+    const int k1 = min(k0 + a.kz, a.nz);
+    const int i = i0 + tx, j = j0 + ty;
+    const bool active = (i < a.nx) & (j < a.ny);
+
+    // own column (remapped so that columns just past the grid edge hold the
+    // ghost values their active neighbours need)
+    const long long own = (long long)remap_index(j, a.ny, a.per[1]) * a.nx +
+                          remap_index(i, a.nx, a.per[0]);
+    // halo cells of this thread (fixed over the march): LDS slot and offset
+    constexpr int HPT = (NH + NT - 1) / NT;  // halo cells per thread
+    int h_slot[HPT];
+    long long h_off[HPT];
+#pragma unroll
+    for (int m = 0; m < HPT; ++m) {
+        const int h = t + m * NT;
+        h_slot[m] = 0;
+        h_off[m] = 0;
+        if (h < NH) {
+            int lx, ly;
+            if (h < NHX) {
+                const int r = h >> 2, s = h & 3;
+                lx = s < 2 ? s : TX + s;
+                ly = r + HY;
+            } else {
+                const int hy = h - NHX;
+                const int r4 = hy / TX, c = hy % TX;
+                lx = c + 2;
+                ly = r4 < 2 ? r4 : TY + r4;
+            }
+            h_slot[m] = ly * PX + lx;
+            const int gi = remap_index(i0 + lx - 2, a.nx, a.per[0]);
+            const int gj = remap_index(j0 + ly - HY, a.ny, a.per[1]);
+            h_off[m] = (long long)gj * a.nx + gi;
+        }
+    }
+    const int own_slot = (ty + HY) * PX + tx + 2;
+    bool ok = true;
+
+    auto zoff = [&](int k) -> long long {
+        return (long long)remap_index(k, a.nz, a.per[2]) * a.nxy;
+    };
+    auto prim_at = [&](long long c, T *v) {
+        T u[NQ];
+        load_cell(a.uin, a.ncell, c, u);
+        ok &= cons_to_prim(u, a.ph, v);
+    };
+    auto slope9 = [&](const T *vm, const T *v0, const T *vp, T *s) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s[q] = limited_slope(v0[q] - vm[q], vp[q] - v0[q], a.ph.limiter);
+    };
+
+    // z window
+    T V0[NQ], Vp1[NQ], D0[NQ], Fzm[NQ];
+    if (NDIM == 3) {
+        T Vm2[NQ], Vm1[NQ], Dm1[NQ], VL[NQ], VR[NQ];
+        prim_at(zoff(k0 - 2) + own, Vm2);
+        prim_at(zoff(k0 - 1) + own, Vm1);
+        prim_at(zoff(k0) + own, V0);
+        prim_at(zoff(k0 + 1) + own, Vp1);
+        slope9(Vm2, Vm1, V0, Dm1);
+        slope9(Vm1, V0, Vp1, D0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            VL[q] = Vm1[q] + T(0.5) * Dm1[q];
+            VR[q] = V0[q] - T(0.5) * D0[q];
+        }
+        face_flux<T, SOLVER>(VL, VR, 2, a.ph, Fzm);
+    } else {
+        prim_at(own, V0);
+    }
+
+    double smax = 0.0, cmax = 0.0;
+    double sum[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sum[q] = 0.0;
+
+    for (int k = k0; k < k1; ++k) {
+        const long long zk = zoff(k);
+        // (a) primitives of plane k into LDS: own column and halo cell
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) P[q * PLANE + own_slot] = V0[q];
+#pragma unroll
+        for (int m = 0; m < HPT; ++m) {
+            if (t + m * NT < NH) {
+                T hv[NQ];
+                prim_at(zk + h_off[m], hv);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) P[q * PLANE + h_slot[m]] = hv[q];
+            }
+        }
+        // (b) z-face k+1/2 from the register window
+        T Fzp[NQ], D1[NQ];
+        if (NDIM == 3) {
+            T Vp2[NQ], VL[NQ], VR[NQ];
+            prim_at(zoff(k + 2) + own, Vp2);
+            slope9(V0, Vp1, Vp2, D1);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                VL[q] = V0[q] + T(0.5) * D0[q];
+                VR[q] = Vp1[q] - T(0.5) * D1[q];
+            }
+            face_flux<T, SOLVER>(VL, VR, 2, a.ph, Fzp);
+            // slide the window: V(k+1), V(k+2) become V(k), V(k+1)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                V0[q] = Vp1[q];
+                Vp1[q] = Vp2[q];
+            }
+        }
+        __syncthreads();
+        // (c) x- and y-faces of the plane
+        for (int it = t; it < NFX + NFY; it += NT) {
+            int d, base, stride;
+            T *dst;
+            if (it < NFX) {
+                const int r = it / (TX + 1), f = it - r * (TX + 1);
+                d = 0;
+                base = (r + HY) * PX + f;  // cells f-2 .. f+1 of row r
+                stride = 1;
+                dst = &FXs[r * (TX + 1) + f];
+            } else {
+                const int it2 = it - NFX;
+                const int r = it2 / TX, c = it2 - r * TX;
+                d = 1;
+                base = r * PX + c + 2;     // rows r-2 .. r+1 of column c
+                stride = PX;
+                dst = &FYs[r * TX + c];
+            }
+            T VL[NQ], VR[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const T *pq = &P[q * PLANE + base];
+                const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride];
+                const T s1 = limited_slope(w1 - w0, w2 - w1, a.ph.limiter);
+                const T s2 = limited_slope(w2 - w1, w3 - w2, a.ph.limiter);
+                VL[q] = w1 + T(0.5) * s1;
+                VR[q] = w2 - T(0.5) * s2;
+            }
+            T F[NQ];
+            face_flux<T, SOLVER>(VL, VR, d, a.ph, F);
+            const int fstride = d == 0 ? TY * (TX + 1) : (TY + 1) * TX;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) dst[q * fstride] = F[q];
+        }
+        __syncthreads();
+        // (d) divergence and stage combine
+        if (active) {
+            const long long c = zk + own;
+            T L[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const T *fx = &FXs[q * TY * (TX + 1) + ty * (TX + 1) + tx];
+                T l = (fx[0] - fx[1]) * a.idx[0];
+                if (NDIM >= 2) {
+                    const T *fy = &FYs[q * (TY + 1) * TX + ty * TX + tx];
+                    l += (fy[0] - fy[TX]) * a.idx[1];
+                }
+                if (NDIM == 3) l += (Fzm[q] - Fzp[q]) * a.idx[2];
+                L[q] = l;
+            }
+            T out[NQ];
+            if (STAGE == 1) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) out[q] = a.uin[q * a.ncell + c] + a.dt * L[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    out[q] = T(0.5) * ((a.un[q * a.ncell + c] + a.uin[q * a.ncell + c]) + a.dt * L[q]);
+                out[PSI] *= a.damp;
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) a.uout[q * a.ncell + c] = out[q];
+            if (STAGE == 2) {
+                ok &= cell_speeds<T, NDIM>(out, a.gamma_d, a.idx_d, smax, cmax);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) sum[q] += (double)out[q];
+            }
+        }
+        if (NDIM == 3) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                Fzm[q] = Fzp[q];
+                D0[q] = D1[q];
+            }
+        }
+    }
+
+    if (!ok) atomicOr(a.flag, 1);
+
+    if (STAGE == 2) {
+        // block reduction of the partials in a fixed order
+        __syncthreads();
+        double *red = reinterpret_cast<double *>(P);  // LDS reuse, TY * NPART doubles
+        double vals[NPART];
+        vals[0] = wave_max(smax);
+        vals[1] = wave_max(cmax);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) vals[2 + q] = wave_sum(sum[q]);
+        if (tx == 0) {
+#pragma unroll
+            for (int e = 0; e < NPART; ++e) red[ty * NPART + e] = vals[e];
+        }
+        __syncthreads();
+        if (t < NPART) {
+            double r = red[t];
+            for (int w = 1; w < TY; ++w) {
+                const double x = red[w * NPART + t];
+                r = t < 2 ? __builtin_fmax(r, x) : r + x;
+            }
+            a.part[(long long)t * a.nblocks + lb] = r;
+        }
+    }
+}
+
+} // namespace mhd

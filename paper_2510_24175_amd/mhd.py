@@ -1,0 +1,241 @@
+"""ctypes binding of the C ABI in ``include/mhd.h`` (``libmhd.so``).
+
+Argument marshalling only: every operation runs in the HIP kernels of the
+library.  Tensors are PyTorch device tensors (PyTorch supplies device memory
+and the HIP stream); shapes are ``(9, nz, ny, nx)`` contiguous.  There is no
+fallback: when the library or a gfx950 device is missing, calls raise.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhd.so")
+
+MHD_OK = 0
+MHD_ERR_ARG = -1
+MHD_ERR_NO_DEVICE = -2
+MHD_ERR_HIP = -3
+MHD_ERR_NONPHYSICAL = -4
+MHD_ERR_UNSUPPORTED = -5
+
+MHD_F32, MHD_F64 = 0, 1
+MHD_HLL, MHD_HLLD = 0, 1
+MHD_MINMOD, MHD_MC = 0, 1
+MHD_PERIODIC, MHD_OUTFLOW = 0, 1
+
+_RIEMANN = {"hll": MHD_HLL, "hlld": MHD_HLLD}
+_LIMITER = {"minmod": MHD_MINMOD, "mc": MHD_MC}
+_BC = {"periodic": MHD_PERIODIC, "outflow": MHD_OUTFLOW}
+_DTYPE = {"f32": MHD_F32, "f64": MHD_F64}
+TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64}
+
+
+class mhd_config(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("riemann", ctypes.c_int32),
+        ("limiter", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("bc", (ctypes.c_int32 * 2) * 3),
+        ("glm", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("glm_alpha", ctypes.c_double),
+    ]
+
+
+class MHDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+_lib = None
+
+
+def load_library():
+    """Load libmhd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2510_24175_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "mhd_init": ([ctypes.POINTER(mhd_config), vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "mhd_destroy": ([vp], None),
+        "mhd_set_stream": ([vp, vp], ctypes.c_int),
+        "mhd_prim_to_cons": ([vp, vp, vp], ctypes.c_int),
+        "mhd_cfl_dt": ([vp, vp, dp], ctypes.c_int),
+        "mhd_step": ([vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], ctypes.c_int),
+        "mhd_step_info": ([vp, dp], ctypes.c_int),
+        "mhd_step_adjoint": ([vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+                             ctypes.c_int),
+        "mhd_prim_to_cons_adjoint": ([vp, vp, vp, vp], ctypes.c_int),
+        "mhd_timing_start": ([vp, ctypes.c_int32], ctypes.c_int),
+        "mhd_timing_stop": ([vp, dp], ctypes.c_int),
+        "mhd_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "mhd_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def make_config(setup, dtype="f32"):
+    c = mhd_config()
+    c.ndim = int(setup["ndim"])
+    c.dtype = _DTYPE[dtype]
+    c.riemann = _RIEMANN[setup["riemann"]]
+    c.limiter = _LIMITER[setup.get("limiter", "minmod")]
+    for d in range(3):
+        c.n[d] = int(setup["n"][d])
+        c.lo[d] = float(setup["lo"][d])
+        c.hi[d] = float(setup["hi"][d])
+        for s in range(2):
+            c.bc[d][s] = _BC[setup["bc"][d][s]]
+    c.glm = 1 if setup.get("glm", True) else 0
+    c.reserved = 0
+    c.gamma = float(setup["gamma"])
+    c.cfl = float(setup["cfl"])
+    c.glm_alpha = float(setup.get("glm_alpha", 0.1))
+    return c
+
+
+def _stream_handle(stream=None):
+    """HIP stream handle: the given torch stream, else torch's current one
+    (the null stream when no device is visible, so mhd_init can report it)."""
+    if stream is None:
+        if not torch.cuda.is_available():
+            return ctypes.c_void_p(0)
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One grid and precision on the current device (see mhd_init)."""
+
+    def __init__(self, setup, dtype="f32", stream=None):
+        self.lib = load_library()
+        self.setup = dict(setup)
+        self.dtype = dtype
+        self.tdtype = TORCH_DTYPE[dtype]
+        self.cfg = make_config(setup, dtype)
+        self.shape = (9, int(setup["n"][2]), int(setup["n"][1]), int(setup["n"][0]))
+        ndim = int(setup["ndim"])
+        dx = [(setup["hi"][d] - setup["lo"][d]) / setup["n"][d] for d in range(3)]
+        self.dh_min = min(dx[d] for d in range(ndim))
+        self.cell_volume = math.prod(dx[d] for d in range(ndim))
+        self.glm = bool(setup.get("glm", True))
+        self.glm_alpha = float(setup.get("glm_alpha", 0.1))
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.mhd_init(ctypes.byref(self.cfg), _stream_handle(stream), ctypes.byref(h))
+        if st != MHD_OK:
+            raise MHDError(st, "mhd_init: " + self.lib.mhd_status_string(st).decode())
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.mhd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ----------------------------------------------------------
+    def _check(self, st, what):
+        if st != MHD_OK:
+            msg = self.lib.mhd_last_error(self.handle).decode()
+            raise MHDError(st, f"{what}: {self.lib.mhd_status_string(st).decode()}: {msg}")
+
+    def _ptr(self, x, dtype=None, what="array"):
+        if x is None:
+            return None
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError(f"{what} must be a device tensor")
+        if tuple(x.shape) != self.shape:
+            raise ValueError(f"{what} has shape {tuple(x.shape)}, expected {self.shape}")
+        if x.dtype != (dtype or self.tdtype):
+            raise TypeError(f"{what} has dtype {x.dtype}, expected {dtype or self.tdtype}")
+        if not x.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        return ctypes.c_void_p(x.data_ptr())
+
+    def empty(self, dtype=None):
+        return torch.empty(self.shape, dtype=dtype or self.tdtype, device="cuda")
+
+    def damp(self, dt, ch):
+        """GLM decay factor exp(-alpha c_h dt / dh_min) for one step."""
+        if not self.glm:
+            return 1.0
+        return math.exp(-self.glm_alpha * ch * dt / self.dh_min)
+
+    # -- C ABI --------------------------------------------------------------
+    def set_stream(self, stream):
+        self.stream = stream
+        self._check(self.lib.mhd_set_stream(self.handle, _stream_handle(stream)), "mhd_set_stream")
+
+    def prim_to_cons(self, V, U=None):
+        U = self.empty() if U is None else U
+        self._check(self.lib.mhd_prim_to_cons(self.handle, self._ptr(V, torch.float64, "V"),
+                                              self._ptr(U, what="U")), "mhd_prim_to_cons")
+        return U
+
+    def cfl_dt(self, U):
+        out = (ctypes.c_double * 2)()
+        self._check(self.lib.mhd_cfl_dt(self.handle, self._ptr(U, what="U"), out), "mhd_cfl_dt")
+        return out[0], out[1]
+
+    def step(self, Un, U_next, dt, ch, damp=None, U1_out=None):
+        if damp is None:
+            damp = self.damp(dt, ch)
+        self._check(self.lib.mhd_step(self.handle, self._ptr(Un, what="Un"),
+                                      self._ptr(U_next, what="U_next"),
+                                      self._ptr(U1_out, what="U1_out"), float(dt), float(ch),
+                                      float(damp)), "mhd_step")
+        return U_next
+
+    def step_info(self):
+        """(dt_next, c_h_next, sums[9]) reduced on the last step's output."""
+        out = (ctypes.c_double * 11)()
+        self._check(self.lib.mhd_step_info(self.handle, out), "mhd_step_info")
+        return out[0], out[1], list(out[2:11])
+
+    def step_adjoint(self, Un, U1, lam_next, lam_n, dt, ch, damp):
+        self._check(self.lib.mhd_step_adjoint(self.handle, self._ptr(Un, what="Un"),
+                                              self._ptr(U1, what="U1"),
+                                              self._ptr(lam_next, torch.float64, "lam_next"),
+                                              self._ptr(lam_n, torch.float64, "lam_n"), float(dt),
+                                              float(ch), float(damp)), "mhd_step_adjoint")
+        return lam_n
+
+    def prim_to_cons_adjoint(self, V, lam_U, lam_V=None):
+        lam_V = self.empty(torch.float64) if lam_V is None else lam_V
+        self._check(self.lib.mhd_prim_to_cons_adjoint(
+            self.handle, self._ptr(V, torch.float64, "V"), self._ptr(lam_U, torch.float64, "lam_U"),
+            self._ptr(lam_V, torch.float64, "lam_V")), "mhd_prim_to_cons_adjoint")
+        return lam_V
+
+    def timing_start(self, capacity):
+        self._check(self.lib.mhd_timing_start(self.handle, int(capacity)), "mhd_timing_start")
+
+    def timing_stop(self):
+        """(steps, stage1_ms, stage2_ms, reduce_ms) totals over the timed steps."""
+        out = (ctypes.c_double * 4)()
+        self._check(self.lib.mhd_timing_stop(self.handle, out), "mhd_timing_stop")
+        return int(out[0]), out[1], out[2], out[3]

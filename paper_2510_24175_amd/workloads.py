@@ -198,9 +198,10 @@ def _sample_mode_sum(setup, modes, coeffs, kmax=4):
             C[k[2] + kmax, k[1] + kmax, k[0] + kmax] += c[a]
         # G[kz, y, x] = sum_{ky,kx} C[kz,ky,kx] Ey[ky,y] Ex[kx,x]
         G = np.einsum("zab,ay,bx->zyx", C, Ey, Ex, optimize=True).reshape(K, ny * nx)
-        # f[z, yx] = Re sum_kz Ez[kz, z] G[kz, yx]
-        f = Ez.real.T @ G.real - Ez.imag.T @ G.imag
-        out[a] = f.reshape(nz, ny, nx)
+        # f[z, yx] = Re sum_kz Ez[kz, z] G[kz, yx], as one real product
+        A = np.concatenate([Ez.real.T, -Ez.imag.T], axis=1)           # (nz, 2K)
+        B = np.concatenate([G.real, G.imag], axis=0)                  # (2K, ny*nx)
+        np.matmul(A, B, out=out[a].reshape(nz, ny * nx))
     return out
 
 

@@ -1,0 +1,34 @@
+"""Shared test helpers: comparison metrics and GPU availability."""
+import os
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def rel_l1(gpu, ref, ch=None):
+    """Relative L1 error per component: sum|q - q_ref| / sum|q_ref| for the 8
+    MHD components; psi is normalised by c_h * sum|B| (psi starts at zero).
+    Returns the array of 9 values."""
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    out = np.empty(9)
+    for q in range(8):
+        den = np.abs(ref[q]).sum()
+        num = np.abs(gpu[q] - ref[q]).sum()
+        out[q] = num / den if den > 0 else num
+    den = (ch if ch else 1.0) * sum(np.abs(ref[q]).sum() for q in (5, 6, 7))
+    out[8] = np.abs(gpu[8] - ref[8]).sum() / den if den > 0 else np.abs(gpu[8] - ref[8]).sum()
+    return out
+
+
+def have_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+requires_gpu = pytest.mark.skipif(not have_gpu(), reason="needs a GPU")

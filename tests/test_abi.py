@@ -1,0 +1,90 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point the header declares, and rejects invalid arguments before touching a
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2510_24175_amd import mhd, workloads as W
+from tests.helpers import ROOT, have_gpu
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "mhd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mhd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mhd.load_library()
+    names = header_functions()
+    assert len(names) >= 11, names
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in mhd.h but not exported"
+
+
+def test_status_strings():
+    lib = mhd.load_library()
+    for st in range(-5, 1):
+        assert lib.mhd_status_string(st)
+    assert lib.mhd_status_string(0) == b"ok"
+
+
+def _init(cfg):
+    lib = mhd.load_library()
+    h = ctypes.c_void_p()
+    st = lib.mhd_init(ctypes.byref(cfg), None, ctypes.byref(h))
+    if h:
+        lib.mhd_destroy(h)
+    return st
+
+
+def _base():
+    s, _ = W.turbulence(8)
+    return mhd.make_config(s, "f32")
+
+
+@pytest.mark.parametrize("field,value", [
+    ("ndim", 0), ("ndim", 4), ("dtype", 7), ("riemann", 3), ("limiter", 9), ("glm", 2),
+    ("reserved", 1), ("gamma", 1.0), ("cfl", 0.0), ("cfl", 1.5), ("glm_alpha", -0.1),
+])
+def test_invalid_config_is_rejected_before_device_use(field, value):
+    cfg = _base()
+    setattr(cfg, field, value)
+    assert _init(cfg) == mhd.MHD_ERR_ARG
+
+
+def test_invalid_geometry_is_rejected():
+    cfg = _base()
+    cfg.n[2] = 1  # active axis with one cell
+    assert _init(cfg) == mhd.MHD_ERR_ARG
+    cfg = _base()
+    cfg.hi[1] = cfg.lo[1]
+    assert _init(cfg) == mhd.MHD_ERR_ARG
+    cfg = _base()
+    cfg.bc[0][0] = mhd.MHD_PERIODIC
+    cfg.bc[0][1] = mhd.MHD_OUTFLOW
+    assert _init(cfg) == mhd.MHD_ERR_ARG
+    s, _ = W.orszag_tang(8)
+    cfg = mhd.make_config(s, "f64")
+    cfg.n[2] = 3  # inactive axis must have one cell
+    assert _init(cfg) == mhd.MHD_ERR_ARG
+
+
+def test_null_arguments():
+    lib = mhd.load_library()
+    assert lib.mhd_init(None, None, None) == mhd.MHD_ERR_ARG
+    assert lib.mhd_step(None, None, None, None, 1.0, 1.0, 1.0) == mhd.MHD_ERR_ARG
+    assert lib.mhd_cfl_dt(None, None, None) == mhd.MHD_ERR_ARG
+    lib.mhd_destroy(None)
+
+
+@pytest.mark.skipif(have_gpu(), reason="checks the no-device path")
+def test_no_device_is_reported():
+    assert _init(_base()) == mhd.MHD_ERR_NO_DEVICE
+    s, _ = W.turbulence(8)
+    with pytest.raises(mhd.MHDError) as e:
+        mhd.Context(s, "f32")
+    assert e.value.status == mhd.MHD_ERR_NO_DEVICE

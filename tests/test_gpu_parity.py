@@ -1,0 +1,185 @@
+"""GPU path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: relative L1 per component (psi normalised by c_h sum|B|) after the
+full run, <= 1e-10 with FP64 state and <= 1e-5 with FP32 state; bitwise for
+uniform states and run-to-run repeats.  Shapes are ragged on purpose
+(several 64 x TY tiles plus partial tiles, z chunks with a partial tail).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import coracle as C
+from paper_2510_24175_amd import workloads as W
+from tests.helpers import rel_l1
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return torch
+
+
+def _gpu_run(torch, setup, V, dtype, nsteps=None, t_end=None):
+    from paper_2510_24175_amd.mhd import Context
+    from paper_2510_24175_amd.rollout import advance
+    ctx = Context(setup, dtype)
+    Vd = torch.from_numpy(V).cuda()
+    U0 = ctx.prim_to_cons(Vd)
+    U, t, hist = advance(ctx, U0, nsteps=nsteps, t_end=t_end)
+    torch.cuda.synchronize()
+    return ctx, U.double().cpu().numpy(), t, hist
+
+
+def _oracle_run(setup, V, nsteps=None, t_end=None):
+    o = C.Oracle(setup)
+    U, t, hist = o.run(o.prim_to_cons(V), nsteps=nsteps, t_end=t_end)
+    return o, U, t, hist
+
+
+def _compare(torch, name, setup, V, dtype, nsteps=None, t_end=None, tol=None):
+    _say(f"[gpu-parity] {name} dtype={dtype} n={setup['n']} steps={nsteps} t_end={t_end}")
+    _, Ug, tg, hg = _gpu_run(torch, setup, V, dtype, nsteps, t_end)
+    _, Uo, to, ho = _oracle_run(setup, V, nsteps, t_end)
+    assert len(hg) == len(ho)
+    err = rel_l1(Ug, Uo, ch=ho[-1][1])
+    _say(f"    rel L1 per component: {np.array2string(err, precision=2)}")
+    assert err.max() <= (tol or TOL[dtype]), err
+    dts = np.array([h[0] for h in hg]) / np.array([h[0] for h in ho]) - 1
+    assert np.abs(dts).max() <= (1e-12 if dtype == "f64" else 1e-5)
+    return err
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_brio_wu(torch_cuda, dtype):
+    s, V = W.brio_wu(400)
+    _compare(torch_cuda, "brio_wu", s, V, dtype, t_end=s["t_end"])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("riemann", ["hlld", "hll"])
+def test_turbulence_ragged_100_steps(torch_cuda, dtype, riemann):
+    # 3 x-tiles (64, 64, 2), a partial last y-tile for both tile heights (8 and 4),
+    # z chunks of 4 planes with a 3-plane tail
+    s, V = W.turbulence((130, 37, 23), riemann=riemann)
+    _compare(torch_cuda, "turbulence", s, V, dtype, nsteps=100)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_turbulence_mc_outflow(torch_cuda, dtype):
+    s, V = W.turbulence((70, 20, 13))
+    s["limiter"] = "mc"
+    s["bc"] = (("outflow", "outflow"), ("periodic", "periodic"), ("outflow", "outflow"))
+    _compare(torch_cuda, "turbulence-mc-outflow", s, V, dtype, nsteps=30)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_orszag_tang_ragged(torch_cuda, dtype):
+    s, V = W.orszag_tang((100, 72))
+    _compare(torch_cuda, "orszag_tang", s, V, dtype, nsteps=200)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_no_glm(torch_cuda, dtype):
+    s, V = W.turbulence((33, 17, 9), riemann="hlld")
+    s["glm"] = False
+    _compare(torch_cuda, "turbulence-noglm", s, V, dtype, nsteps=40)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_uniform_state_bitwise(torch_cuda, dtype, ndim):
+    torch = torch_cuda
+    from paper_2510_24175_amd.mhd import Context
+    from paper_2510_24175_amd.rollout import advance
+    n = {1: (100,), 2: (70, 9), 3: (70, 9, 5)}[ndim]
+    s, V = W.uniform(n, ndim=ndim)
+    _say(f"[gpu-parity] uniform ndim={ndim} dtype={dtype}")
+    ctx = Context(s, dtype)
+    U0 = ctx.prim_to_cons(torch.from_numpy(V).cuda())
+    U, _, _ = advance(ctx, U0, nsteps=100)
+    assert torch.equal(U, U0)
+
+
+def test_run_to_run_bitwise(torch_cuda):
+    torch = torch_cuda
+    s, V = W.turbulence((40, 40, 40))
+    _say("[gpu-parity] determinism 40^3 f32")
+    outs = []
+    for _ in range(2):
+        _, U, _, _ = _gpu_run(torch, s, V, "f32", nsteps=10)
+        outs.append(U)
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_cfl_and_sums_against_oracle(torch_cuda, dtype):
+    torch = torch_cuda
+    from paper_2510_24175_amd.mhd import Context
+    s, V = W.turbulence((48, 40, 36))
+    _say(f"[gpu-parity] cfl/sums dtype={dtype}")
+    ctx = Context(s, dtype)
+    o = C.Oracle(s)
+    Uo = o.prim_to_cons(V)
+    Ug = ctx.prim_to_cons(torch.from_numpy(V).cuda())
+    dt_g, ch_g = ctx.cfl_dt(Ug)
+    dt_o, ch_o = o.cfl(Uo)
+    tol = 1e-14 if dtype == "f64" else 1e-6
+    assert abs(dt_g / dt_o - 1) <= tol and abs(ch_g / ch_o - 1) <= tol
+    Un = torch.empty_like(Ug)
+    ctx.step(Ug, Un, dt_o, ch_o)
+    dt2, ch2, sums = ctx.step_info()
+    Uo1 = o.step(Uo, dt_o, ch_o)
+    dt2_o, ch2_o = o.cfl(Uo1)
+    sums_o = o.sums(Uo1)
+    tol = 1e-12 if dtype == "f64" else 1e-6
+    assert abs(dt2 / dt2_o - 1) <= tol and abs(ch2 / ch2_o - 1) <= tol
+    scale = np.array([np.abs(Uo1[q]).sum() for q in range(9)]) * o.cell_volume
+    assert (np.abs(np.array(sums) - sums_o)[:8] / scale[:8]).max() <= tol
+
+
+def test_nonphysical_state_reported(torch_cuda):
+    torch = torch_cuda
+    from paper_2510_24175_amd.mhd import Context, MHDError, MHD_ERR_NONPHYSICAL
+    s, V = W.turbulence((20, 12, 8))
+    _say("[gpu-parity] non-physical flag")
+    ctx = Context(s, "f32")
+    U = ctx.prim_to_cons(torch.from_numpy(V).cuda())
+    bad = U.clone()
+    bad[4, 3, 5, 7] = 0.01  # E below kinetic + magnetic energy: p < 0
+    with pytest.raises(MHDError) as e:
+        ctx.cfl_dt(bad)
+    assert e.value.status == MHD_ERR_NONPHYSICAL
+    dt, ch = ctx.cfl_dt(U)  # flag cleared, good state fine
+    assert dt > 0 and ch > 0
+    out = torch.empty_like(U)
+    ctx.step(bad, out, dt, ch)
+    with pytest.raises(MHDError) as e:
+        ctx.step_info()
+    assert e.value.status == MHD_ERR_NONPHYSICAL
+
+
+def test_step_argument_errors(torch_cuda):
+    torch = torch_cuda
+    from paper_2510_24175_amd.mhd import Context, MHDError, MHD_ERR_ARG
+    s, V = W.turbulence((16, 8, 8))
+    ctx = Context(s, "f64")
+    U = ctx.prim_to_cons(torch.from_numpy(V).cuda())
+    for kw in [dict(dt=0.0, ch=1.0), dict(dt=1e-3, ch=0.0), dict(dt=1e-3, ch=1.0, damp=1.5)]:
+        with pytest.raises(MHDError) as e:
+            ctx.step(U, torch.empty_like(U), **kw)
+        assert e.value.status == MHD_ERR_ARG
+    with pytest.raises(MHDError) as e:
+        ctx.step(U, U, 1e-3, 1.0)
+    assert e.value.status == MHD_ERR_ARG
