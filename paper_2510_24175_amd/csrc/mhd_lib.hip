@@ -54,10 +54,12 @@ mhd_status fail(mhd_ctx *ctx, mhd_status st, const std::string &msg)
             return fail((ctx), MHD_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-// Stage tile rows per workgroup for a state type and dimensionality.
+// Stage tile rows per workgroup: 4 rows (4 waves) so that two workgroups
+// share a compute unit at the kernels' register budget and fill each
+// other's barrier waits; 1 row in 1D.
 template <typename T, int NDIM> constexpr int tile_rows()
 {
-    return NDIM == 1 ? 1 : (sizeof(T) == 4 ? 8 : 4);
+    return NDIM == 1 ? 1 : 4;
 }
 
 struct Launch {
@@ -346,7 +348,7 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
         if (d < cfg->ndim) ctx->cell_volume *= ctx->dx[d];
     }
     ctx->elem = cfg->dtype == MHD_F32 ? 4 : 8;
-    const int ty = cfg->ndim == 1 ? 1 : (cfg->dtype == MHD_F32 ? 8 : 4);
+    const int ty = cfg->ndim == 1 ? 1 : 4;
     const Launch L = plan_stage(ctx, ty);
     ctx->part_cap = std::max(L.nblocks, CFL_MAX_BLOCKS);
     hipError_t e = hipMalloc(&ctx->u1_scratch, (size_t)NQ * ctx->ncell * ctx->elem);

@@ -22,18 +22,30 @@ enum { LIM_MINMOD = 0, LIM_MC = 1 };
 
 template <typename T> struct Num;
 
+// Type-exact elementary operations (the unsuffixed builtins are the double
+// versions and would promote float operands).
 template <> struct Num<float> {
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float abs(float x) { return __builtin_fabsf(x); }
+    static __device__ __forceinline__ float min(float a, float b) { return __builtin_fminf(a, b); }
+    static __device__ __forceinline__ float max(float a, float b) { return __builtin_fmaxf(a, b); }
+    static __device__ __forceinline__ float copysign(float a, float b) { return __builtin_copysignf(a, b); }
     static constexpr float eps = 1.1920928955078125e-7f;
+    static constexpr float big = 3.0e38f;
 };
 
 template <> struct Num<double> {
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double sqrt(double x) { return __builtin_sqrt(x); }
     static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
+    static __device__ __forceinline__ double abs(double x) { return __builtin_fabs(x); }
+    static __device__ __forceinline__ double min(double a, double b) { return __builtin_fmin(a, b); }
+    static __device__ __forceinline__ double max(double a, double b) { return __builtin_fmax(a, b); }
+    static __device__ __forceinline__ double copysign(double a, double b) { return __builtin_copysign(a, b); }
     static constexpr double eps = 2.220446049250313e-16;
+    static constexpr double big = 1.0e300;
 };
 
 // Per-launch constants of the scheme.
@@ -69,17 +81,17 @@ __device__ __forceinline__ bool cons_to_prim(const T *u, const Phys<T> &ph, T *v
     v[BY] = u[BY];
     v[BZ] = u[BZ];
     v[PSI] = u[PSI];
-    const T big = T(3.0e38);
-    return (rho > T(0)) & (rho < big) & (p > T(0)) & (p < big) & (__builtin_fabs(u[PSI]) < big);
+    const T big = Num<T>::big;
+    return (rho > T(0)) & (rho < big) & (p > T(0)) & (p < big) & (Num<T>::abs(u[PSI]) < big);
 }
 
 // Limited slope from the backward difference a and the forward difference b:
 // minmod(a, b), or MC = minmod(2a, 2b, (a+b)/2).
 template <typename T> __device__ __forceinline__ T limited_slope(T a, T b, int limiter)
 {
-    T m = __builtin_fmin(__builtin_fabs(a), __builtin_fabs(b));
-    if (limiter == LIM_MC) m = __builtin_fmin(T(2) * m, T(0.5) * __builtin_fabs(a + b));
-    return (a * b > T(0)) ? __builtin_copysign(m, a) : T(0);
+    T m = Num<T>::min(Num<T>::abs(a), Num<T>::abs(b));
+    if (limiter == LIM_MC) m = Num<T>::min(T(2) * m, T(0.5) * Num<T>::abs(a + b));
+    return (a * b > T(0)) ? Num<T>::copysign(m, a) : T(0);
 }
 
 // Fast magnetosonic speed from rho, p, |B|^2 and B_n^2:
@@ -92,7 +104,7 @@ __device__ __forceinline__ T fast_speed(T rho, T p, T bsq, T bnsq, T gamma, T ir
     const T bn2 = bnsq * irho;
     const T dab = a2 - b2;
     T disc = dab * dab + T(4) * a2 * (b2 - bn2);
-    disc = __builtin_fmax(disc, T(0));
+    disc = Num<T>::max(disc, T(0));
     return Num<T>::sqrt(T(0.5) * (a2 + b2 + Num<T>::sqrt(disc)));
 }
 
@@ -100,17 +112,17 @@ __device__ __forceinline__ T fast_speed(T rho, T p, T bsq, T bnsq, T gamma, T ir
 // its derived energy, total pressure and v.B.
 template <typename T> struct RState {
     T rho, u, v1, v2, p, bn, b1, b2;
-    T irho, E, pt, vb;
+    T irho, bsq, E, pt, vb;
 };
 
 template <typename T>
 __device__ __forceinline__ void rstate_finish(RState<T> &s, const Phys<T> &ph)
 {
     s.irho = Num<T>::rcp(s.rho);
-    const T bsq = s.bn * s.bn + s.b1 * s.b1 + s.b2 * s.b2;
+    s.bsq = s.bn * s.bn + s.b1 * s.b1 + s.b2 * s.b2;
     s.E = s.p * ph.inv_gm1 + T(0.5) * s.rho * (s.u * s.u + s.v1 * s.v1 + s.v2 * s.v2) +
-          T(0.5) * bsq;
-    s.pt = s.p + T(0.5) * bsq;
+          T(0.5) * s.bsq;
+    s.pt = s.p + T(0.5) * s.bsq;
     s.vb = s.u * s.bn + s.v1 * s.b1 + s.v2 * s.b2;
 }
 
@@ -140,8 +152,7 @@ __device__ __forceinline__ void rstate_flux(const RState<T> &s, T *f, T *c)
 template <typename T>
 __device__ __forceinline__ T rstate_fast(const RState<T> &s, const Phys<T> &ph)
 {
-    const T bsq = s.bn * s.bn + s.b1 * s.b1 + s.b2 * s.b2;
-    return fast_speed(s.rho, s.p, bsq, s.bn * s.bn, ph.gamma, s.irho);
+    return fast_speed(s.rho, s.p, s.bsq, s.bn * s.bn, ph.gamma, s.irho);
 }
 
 // HLL flux, Davis bounds clamped to the origin so one formula covers the
@@ -154,8 +165,8 @@ __device__ __forceinline__ void hll_flux(const RState<T> &L, const RState<T> &R,
     rstate_flux(L, FL, UL);
     rstate_flux(R, FR, UR);
     const T cL = rstate_fast(L, ph), cR = rstate_fast(R, ph);
-    const T sL = __builtin_fmin(__builtin_fmin(L.u - cL, R.u - cR), T(0));
-    const T sR = __builtin_fmax(__builtin_fmax(L.u + cL, R.u + cR), T(0));
+    const T sL = Num<T>::min(Num<T>::min(L.u - cL, R.u - cR), T(0));
+    const T sR = Num<T>::max(Num<T>::max(L.u + cL, R.u + cR), T(0));
     const T id = Num<T>::rcp(sR - sL);
 #pragma unroll
     for (int k = 0; k < 8; ++k) F[k] = (sR * FL[k] - sL * FR[k] + sL * sR * (UR[k] - UL[k])) * id;
@@ -163,8 +174,9 @@ __device__ __forceinline__ void hll_flux(const RState<T> &L, const RState<T> &R,
 
 // One side of the HLLD single-star state (Miyoshi & Kusano 2005).
 template <typename T> struct Star {
-    T rho, v1, v2, b1, b2, E, sq; // sq = sqrt(rho*)
-    T vb;                         // v* . B*
+    T rho, v1, v2, b1, b2, E;
+    T sq, isq; // sqrt(rho*) and 1/sqrt(rho*)
+    T vb;      // v* . B*
 };
 
 template <typename T>
@@ -177,7 +189,7 @@ __device__ __forceinline__ void hlld_star(const RState<T> &s, T S, T sM, T pts, 
     const T mm = m * (S - sM);
     const T bn2 = s.bn * s.bn;
     const T D = mm - bn2;
-    const bool degenerate = __builtin_fabs(D) <= T(16) * Num<T>::eps * (__builtin_fabs(mm) + bn2);
+    const bool degenerate = Num<T>::abs(D) <= T(16) * Num<T>::eps * (Num<T>::abs(mm) + bn2);
     const T iD = Num<T>::rcp(D);
     const T cv = s.bn * (sM - s.u) * iD;
     const T cb = (m * su - bn2) * iD;
@@ -187,7 +199,8 @@ __device__ __forceinline__ void hlld_star(const RState<T> &s, T S, T sM, T pts, 
     o.b2 = degenerate ? s.b2 : s.b2 * cb;
     o.vb = sM * s.bn + o.v1 * o.b1 + o.v2 * o.b2;
     o.E = (su * s.E - s.pt * s.u + pts * sM + s.bn * (s.vb - o.vb)) * isd;
-    o.sq = Num<T>::sqrt(o.rho);
+    o.isq = Num<T>::rsqrt(o.rho);
+    o.sq = o.rho * o.isq;
 }
 
 // HLLD flux (Miyoshi & Kusano 2005) with Davis outer speeds.
@@ -196,8 +209,8 @@ __device__ __forceinline__ void hlld_flux(const RState<T> &L, const RState<T> &R
                                           const Phys<T> &ph, T *F)
 {
     const T cL = rstate_fast(L, ph), cR = rstate_fast(R, ph);
-    const T sL = __builtin_fmin(L.u - cL, R.u - cR);
-    const T sR = __builtin_fmax(L.u + cL, R.u + cR);
+    const T sL = Num<T>::min(L.u - cL, R.u - cR);
+    const T sR = Num<T>::max(L.u + cL, R.u + cR);
     const T mL = (sL - L.u) * L.rho, mR = (sR - R.u) * R.rho;
     const T idm = Num<T>::rcp(mR - mL);
     const T sM = (mR * R.u - mL * L.u - R.pt + L.pt) * idm;
@@ -209,9 +222,9 @@ __device__ __forceinline__ void hlld_flux(const RState<T> &L, const RState<T> &R
     hlld_star(R, sR, sM, pts, sr);
 
     const T sgn = bn >= T(0) ? T(1) : T(-1);
-    const T abn = __builtin_fabs(bn);
-    const T ssL = sM - abn * Num<T>::rcp(sl.sq);
-    const T ssR = sM + abn * Num<T>::rcp(sr.sq);
+    const T abn = Num<T>::abs(bn);
+    const T ssL = sM - abn * sl.isq;
+    const T ssR = sM + abn * sr.isq;
     const T iden = Num<T>::rcp(sl.sq + sr.sq);
     const T v1 = (sl.sq * sl.v1 + sr.sq * sr.v1 + (sr.b1 - sl.b1) * sgn) * iden;
     const T v2 = (sl.sq * sl.v2 + sr.sq * sr.v2 + (sr.b2 - sl.b2) * sgn) * iden;

@@ -22,6 +22,8 @@
 // partials.
 #pragma once
 
+#include <type_traits>
+
 #include "mhd_physics.hpp"
 
 namespace mhd {
@@ -105,8 +107,12 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Waves per SIMD the FP32 kernels are compiled for (register budget 168):
+// with 4-wave workgroups three of them share a compute unit.
+template <typename T> constexpr int stage_min_waves() { return sizeof(T) == 4 ? 3 : 1; }
+
 template <typename T, int SOLVER, int NDIM, int STAGE, int TY>
-__global__ void __launch_bounds__(TX *TY) stage_kernel(const StageArgs<T> a)
+__global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(const StageArgs<T> a)
 {
     constexpr int NT = TX * TY;
     constexpr int HY = NDIM >= 2 ? 2 : 0;  // y halo width in LDS
@@ -115,6 +121,8 @@ __global__ void __launch_bounds__(TX *TY) stage_kernel(const StageArgs<T> a)
     constexpr int PLANE = PX * PY;         // LDS elements per component
     constexpr int NFX = TY * (TX + 1);     // x-face items
     constexpr int NFY = NDIM >= 2 ? (TY + 1) * TX : 0;
+    constexpr int NCHX = (NFX + TX - 1) / TX;       // 64-wide chunks of x items
+    constexpr int NCHUNK = NCHX + NFY / TX;          // NFY is a multiple of TX
     constexpr int NHX = 4 * TY;            // x-halo cells
     constexpr int NH = NHX + (NDIM >= 2 ? 4 * TX : 0);
 
@@ -125,6 +133,7 @@ __global__ void __launch_bounds__(TX *TY) stage_kernel(const StageArgs<T> a)
     const int t = threadIdx.x;
     const int tx = t & (TX - 1);
     const int ty = t / TX;
+    const int wave = __builtin_amdgcn_readfirstlane(ty);
     const int lb = logical_block(blockIdx.x, a.nblocks);
     const int tile_x = lb % a.tiles_x;
     const int rest = lb / a.tiles_x;
@@ -181,6 +190,29 @@ __global__ void __launch_bounds__(TX *TY) stage_kernel(const StageArgs<T> a)
     auto slope9 = [&](const T *vm, const T *v0, const T *vp, T *s) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) s[q] = limited_slope(v0[q] - vm[q], vp[q] - v0[q], a.ph.limiter);
+    };
+
+    // One face of the plane from the LDS stencil w0..w3 (stride apart):
+    // limited slopes of w1 and w2, face states, flux, store (dst may be null
+    // for padding items).
+    auto face_item = [&](auto dir, const T *base, int stride, T *dst, int fstride) {
+        constexpr int D = decltype(dir)::value;
+        T VL[NQ], VR[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const T *pq = base + q * PLANE;
+            const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride];
+            const T s1 = limited_slope(w1 - w0, w2 - w1, a.ph.limiter);
+            const T s2 = limited_slope(w2 - w1, w3 - w2, a.ph.limiter);
+            VL[q] = w1 + T(0.5) * s1;
+            VR[q] = w2 - T(0.5) * s2;
+        }
+        T F[NQ];
+        face_flux<T, SOLVER>(VL, VR, D, a.ph, F);
+        if (dst) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) dst[q * fstride] = F[q];
+        }
     };
 
     // z window
@@ -242,39 +274,25 @@ __global__ void __launch_bounds__(TX *TY) stage_kernel(const StageArgs<T> a)
             }
         }
         __syncthreads();
-        // (c) x- and y-faces of the plane
-        for (int it = t; it < NFX + NFY; it += NT) {
-            int d, base, stride;
-            T *dst;
-            if (it < NFX) {
-                const int r = it / (TX + 1), f = it - r * (TX + 1);
-                d = 0;
-                base = (r + HY) * PX + f;  // cells f-2 .. f+1 of row r
-                stride = 1;
-                dst = &FXs[r * (TX + 1) + f];
+        // (c) x- and y-faces of the plane.  Items go out in 64-wide chunks,
+        // one chunk per wave at a time; x items are padded to whole chunks so
+        // every chunk is a single direction and the solver is inlined with a
+        // compile-time frame.
+        for (int ch = wave; ch < NCHUNK; ch += TY) {
+            if (ch < NCHX) {
+                const int it = ch * TX + tx;
+                const bool valid = it < NFX;
+                const int r = valid ? it / (TX + 1) : 0;
+                const int f = valid ? it - r * (TX + 1) : 0;
+                // cells f-2 .. f+1 of row r
+                face_item(std::integral_constant<int, 0>{}, &P[(r + HY) * PX + f], 1, valid ? &FXs[r * (TX + 1) + f] : nullptr,
+                             TY * (TX + 1));
             } else {
-                const int it2 = it - NFX;
-                const int r = it2 / TX, c = it2 - r * TX;
-                d = 1;
-                base = r * PX + c + 2;     // rows r-2 .. r+1 of column c
-                stride = PX;
-                dst = &FYs[r * TX + c];
+                const int it = (ch - NCHX) * TX + tx;
+                const int r = it / TX, c = it - r * TX;
+                // rows r-2 .. r+1 of column c
+                face_item(std::integral_constant<int, 1>{}, &P[r * PX + c + 2], PX, &FYs[r * TX + c], (TY + 1) * TX);
             }
-            T VL[NQ], VR[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const T *pq = &P[q * PLANE + base];
-                const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride];
-                const T s1 = limited_slope(w1 - w0, w2 - w1, a.ph.limiter);
-                const T s2 = limited_slope(w2 - w1, w3 - w2, a.ph.limiter);
-                VL[q] = w1 + T(0.5) * s1;
-                VR[q] = w2 - T(0.5) * s2;
-            }
-            T F[NQ];
-            face_flux<T, SOLVER>(VL, VR, d, a.ph, F);
-            const int fstride = d == 0 ? TY * (TX + 1) : (TY + 1) * TX;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) dst[q * fstride] = F[q];
         }
         __syncthreads();
         // (d) divergence and stage combine
