@@ -113,6 +113,51 @@ def run_gpu(n, dtype, steps, warmup, quiet=False):
     return res
 
 
+def run_adjoint_ratio(n, dtype, steps):
+    """Time mhd_step (forward, with its CFL read-back) and mhd_step_adjoint
+    (given the stage-1 state) on the same state; events on the stream the
+    library enqueues on (torch's current stream)."""
+    import torch
+
+    from paper_2510_24175_amd import workloads
+    from paper_2510_24175_amd.mhd import Context
+
+    setup, V = workloads.turbulence(n)
+    ctx = Context(setup, dtype, adjoint=True)
+    a = ctx.prim_to_cons(torch.from_numpy(V).cuda())
+    del V
+    b = torch.empty_like(a)
+    u1 = torch.empty_like(a)
+    dt, ch = ctx.cfl_dt(a)
+    dmp = ctx.damp(dt, ch)
+    lam = torch.randn(a.shape, dtype=torch.float64, device="cuda") * 1e-3
+    lam_n = torch.empty_like(lam)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(2):  # warm-up
+        ctx.step(a, b, dt, ch, dmp, U1_out=u1)
+        ctx.step_info()
+        ctx.step_adjoint(a, u1, lam, lam_n, dt, ch, dmp)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(steps):
+        ctx.step(a, b, dt, ch, dmp, U1_out=u1)
+        ctx.step_info()
+    ev[1].record()
+    ev[2].record()
+    for _ in range(steps):
+        ctx.step_adjoint(a, u1, lam, lam_n, dt, ch, dmp)
+    ev[3].record()
+    torch.cuda.synchronize()
+    fwd = ev[0].elapsed_time(ev[1]) / steps
+    adj = ev[2].elapsed_time(ev[3]) / steps
+    ctx.close()
+    del a, b, u1, lam, lam_n
+    torch.cuda.empty_cache()
+    return {"n": n, "dtype": dtype, "forward_ms": round(fwd, 4), "adjoint_ms": round(adj, 4),
+            "ratio": round(adj / fwd, 3),
+            "backward_incl_recompute_ratio": round((adj + fwd) / fwd, 3)}
+
+
 def cpu_baseline(n_sample=128, steps=3):
     """FP64 CPU oracle on a bounded sample of the same workload: the
     [0, n_sample)^3 corner of the 512^3 turbulence fields, stepped with the
@@ -148,6 +193,7 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -211,6 +257,10 @@ def main():
             "hbm_frac_step_algorithmic": round(r64["hbm_frac_step"], 4),
             "stage2_ms": round(r64["stage2_ms"], 4),
         }
+    if not args.no_adjoint:
+        # adjoint/forward time ratio at the adjoint workload (128^3 FP32)
+        # and at the benchmark grid
+        out["adjoint"] = [run_adjoint_ratio(128, "f32", 10), run_adjoint_ratio(args.n, "f32", 3)]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -72,6 +72,10 @@ enum { MHD_F32 = 0, MHD_F64 = 1 };       /* storage and bulk arithmetic */
 enum { MHD_HLL = 0, MHD_HLLD = 1 };      /* Riemann solver              */
 enum { MHD_MINMOD = 0, MHD_MC = 1 };     /* slope limiter               */
 enum { MHD_PERIODIC = 0, MHD_OUTFLOW = 1 }; /* boundary per face        */
+/* MHD_FLAG_ADJOINT: mhd_init also allocates the adjoint scratch (an FP64
+ * stage cotangent, 9 doubles per cell, and per-face contributions, 36 state
+ * elements per face and axis); mhd_step_adjoint needs it. */
+enum { MHD_FLAG_ADJOINT = 1 };
 
 typedef struct {
     int32_t ndim;      /* 1, 2 or 3; axes >= ndim must have n = 1            */
@@ -83,7 +87,7 @@ typedef struct {
     double hi[3];      /* domain upper corner; dx_d = (hi-lo)/n              */
     int32_t bc[3][2];  /* per axis, low and high face; periodic on both or none */
     int32_t glm;       /* 1: GLM cleaning on; 0: psi inert, B_n = (B_L+B_R)/2 */
-    int32_t reserved;  /* must be 0                                          */
+    int32_t flags;     /* MHD_FLAG_* bits; other bits must be 0              */
     double gamma;      /* adiabatic index > 1                                */
     double cfl;        /* Courant number C in (0, 1]                         */
     double glm_alpha;  /* GLM damping parameter alpha >= 0                   */
@@ -135,11 +139,18 @@ mhd_status mhd_step_info(mhd_ctx *ctx, double out[11]);
 
 /* Adjoint of mhd_step (async): given lam_next = dJ/dU_next (double), write
  * lam_n = dJ/dUn (double) for the same dt, c_h, damp, which are treated as
- * constants (not differentiated).  U1 is the stage-1 state of that step
- * (from mhd_step's U1_out) or NULL to recompute it.  lam_n must not alias
- * lam_next.  Kinks (limiter switches, Riemann fan regions) take the branch
- * the forward step took; at a tie |a| = |b| the minmod derivative follows
- * the left difference. */
+ * constants (not differentiated):
+ *   mu = D lam_next (psi times damp), lam1 = mu/2 + (dt/2) J_L(U1)^T mu,
+ *   lam_n = mu/2 + lam1 + dt J_L(Un)^T lam1.
+ * U1 is the stage-1 state of that step (from mhd_step's U1_out) or NULL to
+ * recompute it into library scratch.  lam_n must not alias lam_next.  The
+ * context needs MHD_FLAG_ADJOINT (else MHD_ERR_ARG).  Kinks (limiter
+ * switches, Riemann fan regions) take the branch the forward step took; at
+ * a tie |a| = |b| != 0 the minmod derivative follows the left difference;
+ * where a limiter argument is exactly zero the derivative is the one a
+ * central difference sees (1/2 toward each zero argument for minmod, 1 for
+ * MC).  Local derivative arithmetic is in the state type; the per-cell
+ * gathering and the lambda combinations are FP64. */
 mhd_status mhd_step_adjoint(mhd_ctx *ctx, const void *Un, const void *U1, const double *lam_next,
                             double *lam_n, double dt, double c_h, double damp);
 

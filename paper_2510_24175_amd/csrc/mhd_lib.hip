@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/mhd.h"
+#include "mhd_adjoint.hpp"
 #include "mhd_reduce.hpp"
 #include "mhd_stage.hpp"
 
@@ -29,6 +30,10 @@ struct mhd_ctx {
     double *result = nullptr;    // device NPART doubles
     int *flag = nullptr;         // device non-physical flag
     double *host_res = nullptr;  // pinned NPART doubles + flag word
+    double *lam1 = nullptr;      // adjoint: FP64 stage cotangent
+    void *adjC[3] = {nullptr, nullptr, nullptr}; // adjoint: per-face contributions
+    long long nfaces[3] = {0, 0, 0};
+    int nf[3] = {1, 1, 1};
     bool have_step = false;
     double cell_volume = 1.0;
     double dx[3] = {1, 1, 1};
@@ -166,6 +171,120 @@ mhd_status launch_step_nd(mhd_ctx *ctx, const void *un, void *unext, void *u1, d
     }
 }
 
+template <typename T, int SOLVER, int D>
+void launch_adj_face(mhd_ctx *ctx, const T *U, const double *lam, double psi_scale, double ch)
+{
+    AdjArgs<T> a;
+    a.U = U;
+    a.lam = lam;
+    a.psi_scale = psi_scale;
+    a.C = (T *)ctx->adjC[D];
+    a.flag = ctx->flag;
+    for (int d = 0; d < 3; ++d) {
+        a.n[d] = (int)ctx->n[d];
+        a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
+    }
+    a.nxy = ctx->n[0] * ctx->n[1];
+    a.ncell = ctx->ncell;
+    a.nf = ctx->nf[D];
+    a.nfaces = ctx->nfaces[D];
+    a.idx = 1.0 / ctx->dx[D];
+    a.ph = make_phys<T>(ctx, ch);
+    const long long nb = (a.nfaces + 255) / 256;
+    hipLaunchKernelGGL((adj_face_kernel<T, SOLVER, D>), dim3((unsigned)nb), dim3(256), 0, ctx->stream, a);
+}
+
+template <typename T, int NDIM, int PASS>
+void launch_adj_cell(mhd_ctx *ctx, const T *U, const double *lamp, const double *lam1, double *out,
+                     double dt, double damp)
+{
+    AdjCellArgs<T> a;
+    a.U = U;
+    for (int d = 0; d < 3; ++d) {
+        a.C[d] = (const T *)ctx->adjC[d];
+        a.nfaces[d] = ctx->nfaces[d];
+        a.nf[d] = ctx->nf[d];
+        a.n[d] = (int)ctx->n[d];
+        a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
+    }
+    a.ncell = ctx->ncell;
+    a.gm1 = ctx->cfg.gamma - 1.0;
+    a.lamp = lamp;
+    a.lam1 = lam1;
+    a.out = out;
+    a.damp = damp;
+    a.dt = dt;
+    const long long nb = (ctx->ncell + 255) / 256;
+    hipLaunchKernelGGL((adj_cell_kernel<T, NDIM, PASS>), dim3((unsigned)nb), dim3(256), 0, ctx->stream, a);
+}
+
+template <typename T, int SOLVER, int NDIM>
+mhd_status launch_adjoint(mhd_ctx *ctx, const T *un, const T *u1, const double *lamp, double *lamn,
+                          double dt, double ch, double damp)
+{
+    if (!u1) {
+        // recompute the stage-1 state into scratch with the forward kernel
+        constexpr int TY = tile_rows<T, NDIM>();
+        const Launch L = plan_stage(ctx, TY);
+        StageArgs<T> a;
+        a.part = ctx->part;
+        a.flag = ctx->flag;
+        a.nx = (int)ctx->n[0];
+        a.ny = (int)ctx->n[1];
+        a.nz = (int)ctx->n[2];
+        a.nxy = ctx->n[0] * ctx->n[1];
+        a.ncell = ctx->ncell;
+        for (int d = 0; d < 3; ++d) {
+            a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
+            a.idx[d] = (T)(1.0 / ctx->dx[d]);
+            a.idx_d[d] = 1.0 / ctx->dx[d];
+        }
+        a.kz = L.kz;
+        a.tiles_x = L.tiles_x;
+        a.tiles_y = L.tiles_y;
+        a.chunks = L.chunks;
+        a.nblocks = L.nblocks;
+        a.dt = (T)dt;
+        a.damp = (T)damp;
+        a.gamma_d = ctx->cfg.gamma;
+        a.ph = make_phys<T>(ctx, ch);
+        a.uin = un;
+        a.un = un;
+        a.uout = (T *)ctx->u1_scratch;
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, NDIM, 1, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+                           ctx->stream, a);
+        HIP_TRY(ctx, hipGetLastError());
+        u1 = (const T *)ctx->u1_scratch;
+    }
+    // stage-2 pass: lam1 = mu/2 + (dt/2) J_L(U1)^T mu, mu = D lam'
+    launch_adj_face<T, SOLVER, 0>(ctx, u1, lamp, damp, ch);
+    if (NDIM >= 2) launch_adj_face<T, SOLVER, 1>(ctx, u1, lamp, damp, ch);
+    if (NDIM >= 3) launch_adj_face<T, SOLVER, 2>(ctx, u1, lamp, damp, ch);
+    HIP_TRY(ctx, hipGetLastError());
+    launch_adj_cell<T, NDIM, 2>(ctx, u1, lamp, nullptr, ctx->lam1, dt, damp);
+    HIP_TRY(ctx, hipGetLastError());
+    // stage-1 pass: lamn = mu/2 + lam1 + dt J_L(Un)^T lam1
+    launch_adj_face<T, SOLVER, 0>(ctx, un, ctx->lam1, 1.0, ch);
+    if (NDIM >= 2) launch_adj_face<T, SOLVER, 1>(ctx, un, ctx->lam1, 1.0, ch);
+    if (NDIM >= 3) launch_adj_face<T, SOLVER, 2>(ctx, un, ctx->lam1, 1.0, ch);
+    HIP_TRY(ctx, hipGetLastError());
+    launch_adj_cell<T, NDIM, 1>(ctx, un, lamp, ctx->lam1, lamn, dt, damp);
+    HIP_TRY(ctx, hipGetLastError());
+    return MHD_OK;
+}
+
+template <typename T, int SOLVER>
+mhd_status launch_adjoint_nd(mhd_ctx *ctx, const void *un, const void *u1, const double *lamp,
+                             double *lamn, double dt, double ch, double damp)
+{
+    const T *a = (const T *)un, *b = (const T *)u1;
+    switch (ctx->cfg.ndim) {
+    case 1: return launch_adjoint<T, SOLVER, 1>(ctx, a, b, lamp, lamn, dt, ch, damp);
+    case 2: return launch_adjoint<T, SOLVER, 2>(ctx, a, b, lamp, lamn, dt, ch, damp);
+    default: return launch_adjoint<T, SOLVER, 3>(ctx, a, b, lamp, lamn, dt, ch, damp);
+    }
+}
+
 template <typename T>
 mhd_status launch_cfl(mhd_ctx *ctx, const T *U)
 {
@@ -219,7 +338,7 @@ mhd_status check_config(const mhd_config *c, std::string &why)
     if (c->riemann != MHD_HLL && c->riemann != MHD_HLLD) return why = "bad riemann", MHD_ERR_ARG;
     if (c->limiter != MHD_MINMOD && c->limiter != MHD_MC) return why = "bad limiter", MHD_ERR_ARG;
     if (c->glm != 0 && c->glm != 1) return why = "glm must be 0 or 1", MHD_ERR_ARG;
-    if (c->reserved != 0) return why = "reserved must be 0", MHD_ERR_ARG;
+    if ((c->flags & ~MHD_FLAG_ADJOINT) != 0) return why = "unknown flag bits", MHD_ERR_ARG;
     long long cells = 1;
     for (int d = 0; d < 3; ++d) {
         if (d < c->ndim) {
@@ -260,6 +379,9 @@ void free_ctx(mhd_ctx *ctx)
     if (ctx->result) (void)hipFree(ctx->result);
     if (ctx->flag) (void)hipFree(ctx->flag);
     if (ctx->host_res) (void)hipHostFree(ctx->host_res);
+    if (ctx->lam1) (void)hipFree(ctx->lam1);
+    for (int d = 0; d < 3; ++d)
+        if (ctx->adjC[d]) (void)hipFree(ctx->adjC[d]);
     delete ctx;
 }
 
@@ -356,6 +478,15 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->result, NPART * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->flag, sizeof(int));
     if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->host_res, (NPART + 1) * sizeof(double));
+    for (int d = 0; d < 3; ++d) {
+        ctx->nf[d] = d < cfg->ndim ? (int)(cfg->bc[d][0] == MHD_PERIODIC ? cfg->n[d] : cfg->n[d] + 1) : 1;
+        ctx->nfaces[d] = ctx->ncell / cfg->n[d] * ctx->nf[d];
+    }
+    if (e == hipSuccess && (cfg->flags & MHD_FLAG_ADJOINT)) {
+        e = hipMalloc((void **)&ctx->lam1, (size_t)NQ * ctx->ncell * sizeof(double));
+        for (int d = 0; d < cfg->ndim && e == hipSuccess; ++d)
+            e = hipMalloc(&ctx->adjC[d], (size_t)4 * NQ * ctx->nfaces[d] * ctx->elem);
+    }
     if (e == hipSuccess) e = hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
@@ -467,8 +598,16 @@ mhd_status mhd_step_adjoint(mhd_ctx *ctx, const void *Un, const void *U1, const 
     if (!finite_pos(dt)) return fail(ctx, MHD_ERR_ARG, "dt must be finite and > 0");
     if (ctx->cfg.glm && !finite_pos(c_h)) return fail(ctx, MHD_ERR_ARG, "c_h must be finite and > 0");
     if (!(damp > 0.0 && damp <= 1.0)) return fail(ctx, MHD_ERR_ARG, "damp must be in (0, 1]");
-    (void)U1;
-    return fail(ctx, MHD_ERR_UNSUPPORTED, "adjoint step not available yet");
+    if (!(ctx->cfg.flags & MHD_FLAG_ADJOINT))
+        return fail(ctx, MHD_ERR_ARG, "context was created without MHD_FLAG_ADJOINT");
+    if ((const void *)lam_n == Un || (const void *)lam_n == U1)
+        return fail(ctx, MHD_ERR_ARG, "lam_n must not alias a state buffer");
+    const bool f32 = ctx->cfg.dtype == MHD_F32;
+    if (ctx->cfg.riemann == MHD_HLLD)
+        return f32 ? launch_adjoint_nd<float, SOLVER_HLLD>(ctx, Un, U1, lam_next, lam_n, dt, c_h, damp)
+                   : launch_adjoint_nd<double, SOLVER_HLLD>(ctx, Un, U1, lam_next, lam_n, dt, c_h, damp);
+    return f32 ? launch_adjoint_nd<float, SOLVER_HLL>(ctx, Un, U1, lam_next, lam_n, dt, c_h, damp)
+               : launch_adjoint_nd<double, SOLVER_HLL>(ctx, Un, U1, lam_next, lam_n, dt, c_h, damp);
 }
 
 } // extern "C"

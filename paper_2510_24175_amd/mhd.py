@@ -25,6 +25,7 @@ MHD_F32, MHD_F64 = 0, 1
 MHD_HLL, MHD_HLLD = 0, 1
 MHD_MINMOD, MHD_MC = 0, 1
 MHD_PERIODIC, MHD_OUTFLOW = 0, 1
+MHD_FLAG_ADJOINT = 1
 
 _RIEMANN = {"hll": MHD_HLL, "hlld": MHD_HLLD}
 _LIMITER = {"minmod": MHD_MINMOD, "mc": MHD_MC}
@@ -44,7 +45,7 @@ class mhd_config(ctypes.Structure):
         ("hi", ctypes.c_double * 3),
         ("bc", (ctypes.c_int32 * 2) * 3),
         ("glm", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
         ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double),
         ("glm_alpha", ctypes.c_double),
@@ -93,7 +94,7 @@ def load_library():
     return L
 
 
-def make_config(setup, dtype="f32"):
+def make_config(setup, dtype="f32", adjoint=False):
     c = mhd_config()
     c.ndim = int(setup["ndim"])
     c.dtype = _DTYPE[dtype]
@@ -106,7 +107,7 @@ def make_config(setup, dtype="f32"):
         for s in range(2):
             c.bc[d][s] = _BC[setup["bc"][d][s]]
     c.glm = 1 if setup.get("glm", True) else 0
-    c.reserved = 0
+    c.flags = MHD_FLAG_ADJOINT if adjoint else 0
     c.gamma = float(setup["gamma"])
     c.cfl = float(setup["cfl"])
     c.glm_alpha = float(setup.get("glm_alpha", 0.1))
@@ -126,12 +127,13 @@ def _stream_handle(stream=None):
 class Context:
     """One grid and precision on the current device (see mhd_init)."""
 
-    def __init__(self, setup, dtype="f32", stream=None):
+    def __init__(self, setup, dtype="f32", stream=None, adjoint=False):
         self.lib = load_library()
         self.setup = dict(setup)
         self.dtype = dtype
         self.tdtype = TORCH_DTYPE[dtype]
-        self.cfg = make_config(setup, dtype)
+        self.adjoint = adjoint
+        self.cfg = make_config(setup, dtype, adjoint)
         self.shape = (9, int(setup["n"][2]), int(setup["n"][1]), int(setup["n"][0]))
         ndim = int(setup["ndim"])
         dx = [(setup["hi"][d] - setup["lo"][d]) / setup["n"][d] for d in range(3)]

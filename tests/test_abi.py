@@ -48,7 +48,7 @@ def _base():
 
 @pytest.mark.parametrize("field,value", [
     ("ndim", 0), ("ndim", 4), ("dtype", 7), ("riemann", 3), ("limiter", 9), ("glm", 2),
-    ("reserved", 1), ("gamma", 1.0), ("cfl", 0.0), ("cfl", 1.5), ("glm_alpha", -0.1),
+    ("flags", 2), ("gamma", 1.0), ("cfl", 0.0), ("cfl", 1.5), ("glm_alpha", -0.1),
 ])
 def test_invalid_config_is_rejected_before_device_use(field, value):
     cfg = _base()
