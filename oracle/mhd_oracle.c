@@ -578,6 +578,7 @@ int orc_prim_to_cons(const orc_cfg *cfg, const double *V, double *U)
 {
     if (!cfg_ok(cfg)) return 2;
     int64_t nc = ncells(cfg);
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < nc; ++c) {
         double v[NV], u[NV];
         for (int q = 0; q < NV; ++q) v[q] = V[q * nc + c];
@@ -591,13 +592,18 @@ int orc_cons_to_prim(const orc_cfg *cfg, const double *U, double *V)
 {
     if (!cfg_ok(cfg)) return 2;
     int64_t nc = ncells(cfg);
+    int ok = 1;
+#pragma omp parallel for reduction(&& : ok) schedule(static)
     for (int64_t c = 0; c < nc; ++c) {
         double v[NV], u[NV];
         for (int q = 0; q < NV; ++q) u[q] = U[q * nc + c];
-        if (!cons_to_prim(u, cfg->gamma, v)) return 1;
+        if (!cons_to_prim(u, cfg->gamma, v)) {
+            ok = 0;
+            continue;
+        }
         for (int q = 0; q < NV; ++q) V[q * nc + c] = v[q];
     }
-    return 0;
+    return ok ? 0 : 1;
 }
 
 /* out[0] = dt = C / max (|v_d| + c_f,d)/dx_d (not clipped), out[1] = c_h */
@@ -607,12 +613,14 @@ int orc_cfl(const orc_cfg *cfg, const double *U, double *out)
     int64_t nc = ncells(cfg);
     double smax = 0.0, cmax = 0.0;
     int ok = 1;
+    /* maxima do not depend on the order of the cells */
+#pragma omp parallel for reduction(max : smax, cmax) reduction(&& : ok) schedule(static)
     for (int64_t c = 0; c < nc; ++c) {
         double v[NV], u[NV];
         for (int q = 0; q < NV; ++q) u[q] = U[q * nc + c];
         if (!cons_to_prim(u, cfg->gamma, v)) {
             ok = 0;
-            break;
+            continue;
         }
         for (int d = 0; d < cfg->ndim; ++d) {
             double dx = (cfg->hi[d] - cfg->lo[d]) / (double)cfg->n[d];
@@ -648,10 +656,12 @@ int orc_step(const orc_cfg *cfg, const double *Un, double *Unext, double *U1_out
     }
     int st = rhs(cfg, Un, ch, L);
     if (st == 0) {
+#pragma omp parallel for schedule(static)
         for (int64_t a = 0; a < nt; ++a) U1[a] = Un[a] + dt * L[a];
         st = rhs(cfg, U1, ch, L);
     }
     if (st == 0) {
+#pragma omp parallel for schedule(static)
         for (int64_t a = 0; a < nt; ++a) Unext[a] = 0.5 * (Un[a] + U1[a] + dt * L[a]);
         for (int64_t c = 0; c < nc; ++c) Unext[PSI * nc + c] *= damp;
         if (U1_out) memcpy(U1_out, U1, sizeof(double) * nt);

@@ -70,7 +70,7 @@ def test_brio_wu(torch_cuda, dtype):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("riemann", ["hlld", "hll"])
 def test_turbulence_ragged_100_steps(torch_cuda, dtype, riemann):
-    # 3 x-tiles (64, 64, 2), a partial last y-tile for both tile heights (8 and 4),
+    # 3 x-tiles (64, 64, 2), a partial last y-tile for both tile heights (6 and 4),
     # z chunks of 4 planes with a 3-plane tail
     s, V = W.turbulence((130, 37, 23), riemann=riemann)
     _compare(torch_cuda, "turbulence", s, V, dtype, nsteps=100)
