@@ -59,12 +59,13 @@ mhd_status fail(mhd_ctx *ctx, mhd_status st, const std::string &msg)
             return fail((ctx), MHD_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-// Stage tile rows per workgroup: 4 rows (4 waves) so that two workgroups
-// share a compute unit at the kernels' register budget and fill each
-// other's barrier waits; 1 row in 1D.
+// Stage tile rows per workgroup (one wave per row).  FP32: 6 rows, so two
+// workgroups (12 waves) share a compute unit at the 168-VGPR budget and
+// fill each other's barrier waits, with 20 face rounds per 384 cells per
+// plane.  FP64 (register bound at one wave per SIMD): 4 rows.  1D: 1 row.
 template <typename T, int NDIM> constexpr int tile_rows()
 {
-    return NDIM == 1 ? 1 : 4;
+    return NDIM == 1 ? 1 : (sizeof(T) == 4 ? 6 : 4);
 }
 
 struct Launch {
@@ -122,6 +123,7 @@ mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, do
     for (int d = 0; d < 3; ++d) {
         a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
         a.idx[d] = (T)(1.0 / ctx->dx[d]);
+        a.idx_f[d] = (float)(1.0 / ctx->dx[d]);
         a.idx_d[d] = 1.0 / ctx->dx[d];
     }
     a.kz = L.kz;
@@ -237,6 +239,7 @@ mhd_status launch_adjoint(mhd_ctx *ctx, const T *un, const T *u1, const double *
         for (int d = 0; d < 3; ++d) {
             a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
             a.idx[d] = (T)(1.0 / ctx->dx[d]);
+            a.idx_f[d] = (float)(1.0 / ctx->dx[d]);
             a.idx_d[d] = 1.0 / ctx->dx[d];
         }
         a.kz = L.kz;
@@ -470,7 +473,7 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
         if (d < cfg->ndim) ctx->cell_volume *= ctx->dx[d];
     }
     ctx->elem = cfg->dtype == MHD_F32 ? 4 : 8;
-    const int ty = cfg->ndim == 1 ? 1 : 4;
+    const int ty = cfg->ndim == 1 ? 1 : (cfg->dtype == MHD_F32 ? 6 : 4);
     const Launch L = plan_stage(ctx, ty);
     ctx->part_cap = std::max(L.nblocks, CFL_MAX_BLOCKS);
     hipError_t e = hipMalloc(&ctx->u1_scratch, (size_t)NQ * ctx->ncell * ctx->elem);

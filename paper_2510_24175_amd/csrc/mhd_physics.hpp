@@ -115,15 +115,29 @@ template <typename T> struct RState {
     T irho, bsq, E, pt, vb;
 };
 
+// irho, |B|^2 and total pressure of a rotated state
 template <typename T>
-__device__ __forceinline__ void rstate_finish(RState<T> &s, const Phys<T> &ph)
+__device__ __forceinline__ void rstate_prepare(RState<T> &s)
 {
     s.irho = Num<T>::rcp(s.rho);
     s.bsq = s.bn * s.bn + s.b1 * s.b1 + s.b2 * s.b2;
+    s.pt = s.p + T(0.5) * s.bsq;
+}
+
+// total energy and v.B of a prepared rotated state
+template <typename T>
+__device__ __forceinline__ void rstate_energy(RState<T> &s, const Phys<T> &ph)
+{
     s.E = s.p * ph.inv_gm1 + T(0.5) * s.rho * (s.u * s.u + s.v1 * s.v1 + s.v2 * s.v2) +
           T(0.5) * s.bsq;
-    s.pt = s.p + T(0.5) * s.bsq;
     s.vb = s.u * s.bn + s.v1 * s.b1 + s.v2 * s.b2;
+}
+
+template <typename T>
+__device__ __forceinline__ void rstate_finish(RState<T> &s, const Phys<T> &ph)
+{
+    rstate_prepare(s);
+    rstate_energy(s, ph);
 }
 
 // physical normal flux (8 comps, slot 5 unused) and conserved vector
@@ -157,13 +171,17 @@ __device__ __forceinline__ T rstate_fast(const RState<T> &s, const Phys<T> &ph)
 
 // HLL flux, Davis bounds clamped to the origin so one formula covers the
 // supersonic cases: F = (sR FL - sL FR + sL sR (UR - UL)) / (sR - sL).
+// L and R need irho, bsq and pt (rstate_prepare).
 template <typename T>
 __device__ __forceinline__ void hll_flux(const RState<T> &L, const RState<T> &R,
                                          const Phys<T> &ph, T *F)
 {
+    RState<T> Le = L, Re = R;
+    rstate_energy(Le, ph);
+    rstate_energy(Re, ph);
     T FL[8], UL[8], FR[8], UR[8];
-    rstate_flux(L, FL, UL);
-    rstate_flux(R, FR, UR);
+    rstate_flux(Le, FL, UL);
+    rstate_flux(Re, FR, UR);
     const T cL = rstate_fast(L, ph), cR = rstate_fast(R, ph);
     const T sL = Num<T>::min(Num<T>::min(L.u - cL, R.u - cR), T(0));
     const T sR = Num<T>::max(Num<T>::max(L.u + cL, R.u + cR), T(0));
@@ -172,38 +190,49 @@ __device__ __forceinline__ void hll_flux(const RState<T> &L, const RState<T> &R,
     for (int k = 0; k < 8; ++k) F[k] = (sR * FL[k] - sL * FR[k] + sL * sR * (UR[k] - UL[k])) * id;
 }
 
-// One side of the HLLD single-star state (Miyoshi & Kusano 2005).
+// One side of the HLLD single-star state (Miyoshi & Kusano 2005): density,
+// tangential velocity and field.  Its energy is formed only for the side the
+// flux is taken from (hlld_star_energy).
 template <typename T> struct Star {
-    T rho, v1, v2, b1, b2, E;
+    T rho, v1, v2, b1, b2;
+    T su, isd; // S - u and 1/(S - S_M)
     T sq, isq; // sqrt(rho*) and 1/sqrt(rho*)
-    T vb;      // v* . B*
 };
 
 template <typename T>
-__device__ __forceinline__ void hlld_star(const RState<T> &s, T S, T sM, T pts, Star<T> &o)
+__device__ __forceinline__ void hlld_star(const RState<T> &s, T S, T sM, Star<T> &o)
 {
-    const T su = S - s.u;
-    const T isd = Num<T>::rcp(S - sM);
-    const T m = s.rho * su;
-    o.rho = m * isd;
+    o.su = S - s.u;
+    o.isd = Num<T>::rcp(S - sM);
+    const T m = s.rho * o.su;
+    o.rho = m * o.isd;
     const T mm = m * (S - sM);
     const T bn2 = s.bn * s.bn;
     const T D = mm - bn2;
     const bool degenerate = Num<T>::abs(D) <= T(16) * Num<T>::eps * (Num<T>::abs(mm) + bn2);
     const T iD = Num<T>::rcp(D);
     const T cv = s.bn * (sM - s.u) * iD;
-    const T cb = (m * su - bn2) * iD;
+    const T cb = (m * o.su - bn2) * iD;
     o.v1 = degenerate ? s.v1 : s.v1 - s.b1 * cv;
     o.v2 = degenerate ? s.v2 : s.v2 - s.b2 * cv;
     o.b1 = degenerate ? s.b1 : s.b1 * cb;
     o.b2 = degenerate ? s.b2 : s.b2 * cb;
-    o.vb = sM * s.bn + o.v1 * o.b1 + o.v2 * o.b2;
-    o.E = (su * s.E - s.pt * s.u + pts * sM + s.bn * (s.vb - o.vb)) * isd;
     o.isq = Num<T>::rsqrt(o.rho);
     o.sq = o.rho * o.isq;
 }
 
-// HLLD flux (Miyoshi & Kusano 2005) with Davis outer speeds.
+// v*.B* and E* of one side: E* = ((S-u)E - p_T u + p_T* S_M + B_n (v.B - v*.B*)) / (S - S_M)
+template <typename T>
+__device__ __forceinline__ void hlld_star_energy(const RState<T> &s, const Star<T> &o, T sM, T pts,
+                                                 T &vbs, T &Es)
+{
+    vbs = sM * s.bn + o.v1 * o.b1 + o.v2 * o.b2;
+    Es = (o.su * s.E - s.pt * s.u + pts * sM + s.bn * (s.vb - vbs)) * o.isd;
+}
+
+// HLLD flux (Miyoshi & Kusano 2005) with Davis outer speeds.  L and R need
+// irho, bsq and pt (rstate_prepare); E and v.B are formed for the side the
+// flux is taken from.
 template <typename T>
 __device__ __forceinline__ void hlld_flux(const RState<T> &L, const RState<T> &R,
                                           const Phys<T> &ph, T *F)
@@ -218,8 +247,8 @@ __device__ __forceinline__ void hlld_flux(const RState<T> &L, const RState<T> &R
     const T bn = L.bn;
 
     Star<T> sl, sr;
-    hlld_star(L, sL, sM, pts, sl);
-    hlld_star(R, sR, sM, pts, sr);
+    hlld_star(L, sL, sM, sl);
+    hlld_star(R, sR, sM, sr);
 
     const T sgn = bn >= T(0) ? T(1) : T(-1);
     const T abn = Num<T>::abs(bn);
@@ -235,8 +264,9 @@ __device__ __forceinline__ void hlld_flux(const RState<T> &L, const RState<T> &R
 
     // side of the contact and the region within it
     const bool left = sM >= T(0);
-    const RState<T> &S = left ? L : R;
-    const Star<T> &st = left ? sl : sr;
+    RState<T> S = left ? L : R;
+    rstate_energy(S, ph);
+    const Star<T> st = left ? sl : sr;
     const T s_out = left ? sL : sR;
     const T s_in = left ? ssL : ssR;
     // outer region: sL >= 0 (left) or sR <= 0 (right)
@@ -245,11 +275,13 @@ __device__ __forceinline__ void hlld_flux(const RState<T> &L, const RState<T> &R
     const bool dbl = left ? (ssL < T(0)) : (ssR >= T(0));
     const T a1 = outer ? T(0) : s_out;
     const T a2 = (outer || !dbl) ? T(0) : s_in;
-    const T Ess = st.E + (left ? -st.sq : st.sq) * (st.vb - vbss) * sgn;
+    T vbs, Es;
+    hlld_star_energy(S, st, sM, pts, vbs, Es);
+    const T Ess = Es + (left ? -st.sq : st.sq) * (vbs - vbss) * sgn;
 
     T f[8], u[8];
     rstate_flux(S, f, u);
-    const T us[8] = {st.rho, st.rho * sM, st.rho * st.v1, st.rho * st.v2, st.E, bn, st.b1, st.b2};
+    const T us[8] = {st.rho, st.rho * sM, st.rho * st.v1, st.rho * st.v2, Es, bn, st.b1, st.b2};
     const T uss[8] = {st.rho, st.rho * sM, st.rho * v1, st.rho * v2, Ess, bn, b1, b2};
 #pragma unroll
     for (int k = 0; k < 8; ++k) F[k] = f[k] + a1 * (us[k] - u[k]) + a2 * (uss[k] - us[k]);
@@ -296,8 +328,8 @@ __device__ __forceinline__ void face_flux(const T *VL, const T *VR, int d, const
     R.bn = bns;
     R.b1 = pick3(d, VR[BY], VR[BZ], VR[BX]);
     R.b2 = pick3(d, VR[BZ], VR[BX], VR[BY]);
-    rstate_finish(L, ph);
-    rstate_finish(R, ph);
+    rstate_prepare(L);
+    rstate_prepare(R);
     T f[8];
     if (SOLVER == SOLVER_HLLD)
         hlld_flux(L, R, ph, f);
