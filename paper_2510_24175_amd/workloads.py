@@ -249,11 +249,14 @@ def smooth_direction(n, seed, kmax=4):
 
 # ------------------------------------------------------- Orszag-Tang -------
 
-def orszag_tang(n=1024, seed=3, riemann="hlld", cfl=0.4, t_end=0.5):
+def orszag_tang(n=1024, seed=3, riemann="hlld", cfl=0.3, t_end=0.5):
     """2D periodic Orszag & Tang (1979)-type vortex on [0,1]^2:
     rho = 25/(36 pi), p = 5/(12 pi), gamma = 5/3,
     v = (-a1 sin 2pi y, a2 sin 2pi x), B = B0 (-a3 sin 2pi y, a4 sin 4pi x),
-    B0 = 1/sqrt(4 pi), a_i = 1 + 0.05 u_i with u_i ~ U(-1, 1) from the seed."""
+    B0 = 1/sqrt(4 pi), a_i = 1 + 0.05 u_i with u_i ~ U(-1, 1) from the seed.
+    Courant number 0.3: with 0.4 this scheme (PLM minmod + HLLD + GLM, SSP-RK2,
+    no floors) produces a non-positive pressure before t = 0.5 at 512^2 and
+    1024^2."""
     if isinstance(n, int):
         n = (n, n)
     s = make_setup("orszag_tang", 2, n, gamma=5.0 / 3.0, cfl=cfl, riemann=riemann, t_end=t_end)
