@@ -6,21 +6,16 @@
 // Given lam' = dJ/dU_next:   mu  = D lam'
 //                            lam1 = mu/2 + (dt/2) J_L(U1)^T mu
 //                            lamn = mu/2 + lam1 + dt J_L(Un)^T lam1
-// J_L(U)^T v is built in two passes:
-//   * adj_face_kernel<D> (one thread per face along axis D): recompute the
-//     4-cell stencil, PLM face states and the face flux, then take the
-//     flux cotangent g = (v_b - v_a)/dx_D (L_a = -(F_{a+1/2} - ..)/dx) back
-//     through the Riemann solver, the GLM interface solve and the limited
-//     slopes to the primitive cotangents of the 4 stencil cells, written as
-//     4 x 9 contributions per face;
-//   * adj_cell_kernel (one thread per cell): gather, in a fixed order, the
-//     contributions of every (face, stencil position) that maps to the cell
-//     (periodic wrap or outflow clamp), apply the transpose of the
-//     conserved -> primitive Jacobian in FP64, and form lam1 or lamn.
-// Local VJP arithmetic is in the state type T; gathering and the lambda
-// combinations are FP64.  Kinks take the branch the forward took; where a
-// limiter argument is exactly zero the derivative is the one a central
-// difference sees (1/2 toward each zero argument for minmod, 1 for MC).
+// Each line is one fused pass over the grid (adj_stage_kernel below): the
+// face VJPs (recomputed stencil, PLM, GLM interface solve and Riemann
+// solver, reversed) are taken per tile in LDS, the limited-slope reverse and
+// the gather to cells follow in the same workgroup, and the primitive ->
+// conserved transpose and the lambda combination close the pass.
+// Local VJP arithmetic is in the state type T; the transpose to conserved
+// cotangents and the lambda combinations are FP64.  Kinks take the branch
+// the forward took; where a limiter argument is exactly zero the derivative
+// is the one a central difference sees (1/2 toward each zero argument for
+// minmod, 1 for MC).
 #pragma once
 
 #include "mhd_physics.hpp"
@@ -233,6 +228,38 @@ __device__ __forceinline__ void star_rev(const RState<T> &s, T sM, T pts, const 
     sMb -= sdb;
 }
 
+// field-wise selects (a select of references would put both structs in
+// private memory)
+template <typename T>
+__device__ __forceinline__ RState<T> pick_state(bool c, const RState<T> &a, const RState<T> &b)
+{
+    RState<T> o;
+    o.rho = c ? a.rho : b.rho; o.u = c ? a.u : b.u; o.v1 = c ? a.v1 : b.v1; o.v2 = c ? a.v2 : b.v2;
+    o.p = c ? a.p : b.p; o.bn = c ? a.bn : b.bn; o.b1 = c ? a.b1 : b.b1; o.b2 = c ? a.b2 : b.b2;
+    o.irho = c ? a.irho : b.irho; o.bsq = c ? a.bsq : b.bsq; o.E = c ? a.E : b.E;
+    o.pt = c ? a.pt : b.pt; o.vb = c ? a.vb : b.vb;
+    return o;
+}
+template <typename T>
+__device__ __forceinline__ void add_picked(bool c, const RBar<T> &x, const DBar<T> &y, RBar<T> &La,
+                                           DBar<T> &Ld, RBar<T> &Ra, DBar<T> &Rd)
+{
+    const T z = T(0);
+    La.rho += c ? x.rho : z; Ra.rho += c ? z : x.rho;
+    La.u += c ? x.u : z; Ra.u += c ? z : x.u;
+    La.v1 += c ? x.v1 : z; Ra.v1 += c ? z : x.v1;
+    La.v2 += c ? x.v2 : z; Ra.v2 += c ? z : x.v2;
+    La.p += c ? x.p : z; Ra.p += c ? z : x.p;
+    La.bn += c ? x.bn : z; Ra.bn += c ? z : x.bn;
+    La.b1 += c ? x.b1 : z; Ra.b1 += c ? z : x.b1;
+    La.b2 += c ? x.b2 : z; Ra.b2 += c ? z : x.b2;
+    Ld.irho += c ? y.irho : z; Rd.irho += c ? z : y.irho;
+    Ld.bsq += c ? y.bsq : z; Rd.bsq += c ? z : y.bsq;
+    Ld.E += c ? y.E : z; Rd.E += c ? z : y.E;
+    Ld.pt += c ? y.pt : z; Rd.pt += c ? z : y.pt;
+    Ld.vb += c ? y.vb : z; Rd.vb += c ? z : y.vb;
+}
+
 template <typename T>
 __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R, const Phys<T> &ph,
                                          const T *Fb, RBar<T> &Lb, RBar<T> &Rb, DBar<T> &Ld,
@@ -268,8 +295,15 @@ __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R,
     const T b1 = N1 * iden, b2 = N2 * iden;
     const T vbss = sM * bn + v1 * b1 + v2 * b2;
     const bool left = sM >= T(0);
-    const RState<T> &S = left ? L : R;
-    const StarT<T> &st = left ? sl : sr;
+    const RState<T> S = pick_state(left, L, R);
+    StarT<T> st;
+    st.su = left ? sl.su : sr.su; st.sd = left ? sl.sd : sr.sd; st.isd = left ? sl.isd : sr.isd;
+    st.m = left ? sl.m : sr.m; st.rho = left ? sl.rho : sr.rho; st.mm = left ? sl.mm : sr.mm;
+    st.D = left ? sl.D : sr.D; st.iD = left ? sl.iD : sr.iD; st.cv = left ? sl.cv : sr.cv;
+    st.cb = left ? sl.cb : sr.cb; st.v1 = left ? sl.v1 : sr.v1; st.v2 = left ? sl.v2 : sr.v2;
+    st.b1 = left ? sl.b1 : sr.b1; st.b2 = left ? sl.b2 : sr.b2; st.vb = left ? sl.vb : sr.vb;
+    st.Enum = left ? sl.Enum : sr.Enum; st.E = left ? sl.E : sr.E; st.isq = left ? sl.isq : sr.isq;
+    st.sq = left ? sl.sq : sr.sq; st.deg = left ? sl.deg : sr.deg;
     const T s_out = left ? sL : sR;
     const T s_in = left ? ssL : ssR;
     const bool outer = left ? (sL >= T(0)) : (sR <= T(0));
@@ -369,16 +403,18 @@ __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R,
     }
     bnb += sgn * abnb;
     // the side's own star cotangents
-    StarB<T> &sideb = left ? slb : srb;
-    sideb.rho += stb.rho;
-    sideb.v1 += stb.v1;
-    sideb.v2 += stb.v2;
-    sideb.b1 += stb.b1;
-    sideb.b2 += stb.b2;
-    sideb.E += stb.E;
-    sideb.vb += stb.vb;
-    sideb.sq += stb.sq;
-    sideb.isq += stb.isq;
+    {
+        const T z = T(0);
+        slb.rho += left ? stb.rho : z; srb.rho += left ? z : stb.rho;
+        slb.v1 += left ? stb.v1 : z; srb.v1 += left ? z : stb.v1;
+        slb.v2 += left ? stb.v2 : z; srb.v2 += left ? z : stb.v2;
+        slb.b1 += left ? stb.b1 : z; srb.b1 += left ? z : stb.b1;
+        slb.b2 += left ? stb.b2 : z; srb.b2 += left ? z : stb.b2;
+        slb.E += left ? stb.E : z; srb.E += left ? z : stb.E;
+        slb.vb += left ? stb.vb : z; srb.vb += left ? z : stb.vb;
+        slb.sq += left ? stb.sq : z; srb.sq += left ? z : stb.sq;
+        slb.isq += left ? stb.isq : z; srb.isq += left ? z : stb.isq;
+    }
     T sLb = left ? s_out_b : T(0);
     T sRb = left ? T(0) : s_out_b;
     T ptsb = 0;
@@ -408,10 +444,12 @@ __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R,
     if (selx) { Lb.u += sLb; cLb -= sLb; } else { Rb.u += sLb; cRb -= sLb; }
     if (sely) { Lb.u += sRb; cLb += sRb; } else { Rb.u += sRb; cRb += sRb; }
     // flux and conserved vector of the side state (F = f + a1 (us - u) + ...)
-    if (left)
-        flux_rev(L, Fb, ub, Lb, Ld);
-    else
-        flux_rev(R, Fb, ub, Rb, Rd);
+    {
+        RBar<T> xb;
+        DBar<T> xd;
+        flux_rev(S, Fb, ub, xb, xd);
+        add_picked(left, xb, xd, Lb, Ld, Rb, Rd);
+    }
     fast_rev(L, ph, cL, cLb, Lb, Ld);
     fast_rev(R, ph, cR, cRb, Rb, Rd);
 }
@@ -453,15 +491,11 @@ __device__ __forceinline__ void face_flux_vjp(const T *VL, const T *VR, const Ph
     VLb[PRS] = Lb.p; VLb[BX + d1] = Lb.b1; VLb[BX + d2] = Lb.b2;
     VRb[RHO] = Rb.rho; VRb[VX + D] = Rb.u; VRb[VX + d1] = Rb.v1; VRb[VX + d2] = Rb.v2;
     VRb[PRS] = Rb.p; VRb[BX + d1] = Rb.b1; VRb[BX + d2] = Rb.b2;
-    if (ph.glm) {
-        VLb[BX + D] = T(0.5) * bnsb + T(0.5) * ph.ch * psisb;
-        VRb[BX + D] = T(0.5) * bnsb - T(0.5) * ph.ch * psisb;
-        VLb[PSI] = bnsb * ph.half_ich + T(0.5) * psisb;
-        VRb[PSI] = -bnsb * ph.half_ich + T(0.5) * psisb;
-    } else {
-        VLb[BX + D] = VRb[BX + D] = T(0.5) * bnsb;
-        VLb[PSI] = VRb[PSI] = T(0);
-    }
+    // (without GLM, psisb = 0 and ch = half_ich = 0: the psi cotangents vanish)
+    VLb[BX + D] = T(0.5) * bnsb + T(0.5) * ph.ch * psisb;
+    VRb[BX + D] = T(0.5) * bnsb - T(0.5) * ph.ch * psisb;
+    VLb[PSI] = bnsb * ph.half_ich + T(0.5) * psisb;
+    VRb[PSI] = -bnsb * ph.half_ich + T(0.5) * psisb;
 }
 
 // limited slope with its derivative coefficients (dp, dq) w.r.t. the
@@ -489,174 +523,404 @@ __device__ __forceinline__ T slope_d(T a, T b, int limiter, T &dp, T &dq)
     return pos ? m : T(0);
 }
 
-template <typename T> struct AdjArgs {
-    const T *U;           // state the stage VJP linearises about (Un or U1)
-    const double *lam;    // cotangent v of L (lam' for the stage-2 VJP, lam1 for stage 1)
-    double psi_scale;     // damp for the stage-2 VJP (v = D lam'), 1 otherwise
-    T *C;                 // contributions [36][nfaces] of this axis
-    int *flag;
-    int n[3];
+
+// ---------------------------------------------------------------------------
+// Fused adjoint stage.
+//
+// One pass over the grid forms r = J_L(U)^T v for every cell and combines it
+// with mu = D lam':
+//   pass 2 (about U1, v = mu):    lam1 = mu/2 + (dt/2) r
+//   pass 1 (about Un, v = lam1):  lamn = mu/2 + lam1 + dt r
+//
+// Per axis, with face c the lower face of cell c: the flux cotangent is
+// g_f = (v_f - v_{f-1})/dx, and the face VJP returns the cotangents VLb_f,
+// VRb_f of the reconstructed states VL_f = W_{f-1} + s_{f-1}/2 and
+// VR_f = W_f - s_f/2.  With the slope cotangent sb_c = (VLb_{c+1} - VRb_c)/2,
+// (dp_c, dq_c) the derivatives of the limited slope of c with respect to its
+// backward and forward differences, A_c = sb_c dp_c, B_c = sb_c dq_c and
+// E_c = VLb_{c+1} + VRb_c + A_c - B_c, the primitive cotangent of cell c is
+//   Wb_c = E_c - A_{c+1} + B_{c-1}.
+// Positions past the grid follow the boundary rule: periodic wrap; outflow
+// takes the clamped boundary state and a zero v, so faces beyond the
+// boundary faces carry no cotangent, and the ghost cells fold into the
+// boundary cells through four substitutions:
+//   B_{-1} <- VLb_0,  E_0 <- E_0 - A_0,  A_n <- -VRb_n,  E_{n-1} <- E_{n-1} + B_{n-1}.
+//
+// Work decomposition (as the forward stage): a workgroup owns 64 x TY
+// columns and marches along z.  The primitive plane with a 3-cell x/y halo
+// sits in LDS; x- and y-faces (TX + 3 per row, TY + 3 rows per column) are
+// items whose (VLb, VRb) go to LDS; each cell item (own cells plus one halo
+// cell per side) reads its two face slots and overwrites them with (A, B),
+// which the neighbours read after a barrier.  z-faces come from a register
+// window of four planes, the z-direction A, B, E and the partial sum
+// X_k = E_k + B_{k-1} slide along with it (three warm-up faces per chunk).
+// Local VJP arithmetic is in T; the three axis sums, the primitive ->
+// conserved transpose and the lambda combination are FP64.
+// ---------------------------------------------------------------------------
+
+template <typename T> struct AdjStageArgs {
+    const T *U;          // state of the linearisation: U1 (pass 2) or Un (pass 1)
+    const double *lamp;  // lam' = dJ/dU_next
+    const double *lam1;  // pass 1: lam1 (the cotangent v); unused in pass 2
+    double *out;         // pass 2: lam1; pass 1: lamn
+    int *flag;           // non-physical flag
+    int nx, ny, nz;
     long long nxy, ncell;
     int per[3];
-    int nf;               // faces along the axis: n (periodic) or n + 1 (outflow)
-    long long nfaces;
-    double idx;           // 1/dx along the axis
+    int kz, tiles_x, tiles_y, chunks, nblocks;
+    double dt, damp;
+    double idx[3];       // 1/dx per axis
+    double gm1;
     Phys<T> ph;
 };
 
-template <typename T, int SOLVER, int D>
-__global__ void __launch_bounds__(256) adj_face_kernel(const AdjArgs<T> a)
+// cell item of one component: returns E_c (with the outflow substitutions
+// for the boundary cells), sets A_c and B_c (substituted for the ghosts)
+struct CellFlags {
+    bool ghost_lo, first, ghost_hi, last;
+};
+__device__ __forceinline__ CellFlags cell_flags(int c, int n, int per)
 {
-    const long long fid = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (fid >= a.nfaces) return;
-    int e[3] = {a.n[0], a.n[1], a.n[2]};
-    e[D] = a.nf;
-    int c3[3];
-    c3[0] = (int)(fid % e[0]);
-    c3[1] = (int)((fid / e[0]) % e[1]);
-    c3[2] = (int)(fid / ((long long)e[0] * e[1]));
-    const int f = c3[D];
-    const int n = a.n[D];
-    const bool outflow = !a.per[D];
-    auto cell = [&](int pos) -> long long {
-        int c[3] = {c3[0], c3[1], c3[2]};
-        c[D] = remap_index(pos, n, a.per[D]);
-        return ((long long)c[2] * a.n[1] + c[1]) * a.n[0] + c[0];
-    };
-    T W[4][NQ];
-    bool ok = true;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        T u[NQ];
-        load_cell(a.U, a.ncell, cell(f - 2 + m), u);
-        ok &= cons_to_prim(u, a.ph, W[m]);
-    }
-    if (!ok) atomicOr(a.flag, 1);
-    T VL[NQ], VR[NQ], dp1[NQ], dq1[NQ], dp2[NQ], dq2[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const T s1 = slope_d(W[1][q] - W[0][q], W[2][q] - W[1][q], a.ph.limiter, dp1[q], dq1[q]);
-        const T s2 = slope_d(W[2][q] - W[1][q], W[3][q] - W[2][q], a.ph.limiter, dp2[q], dq2[q]);
-        VL[q] = W[1][q] + T(0.5) * s1;
-        VR[q] = W[2][q] - T(0.5) * s2;
-    }
-    // flux cotangent: F enters L_b (+1/dx) and L_a (-1/dx), a = f-1, b = f;
-    // an outflow boundary face has no interior cell on its outer side
-    const bool has_a = !(outflow && f == 0), has_b = !(outflow && f == n);
-    const long long ca = cell(f - 1), cb = cell(f);
-    T gb[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const double sc = q == PSI ? a.psi_scale : 1.0;
-        const double va = has_a ? a.lam[q * a.ncell + ca] : 0.0;
-        const double vb = has_b ? a.lam[q * a.ncell + cb] : 0.0;
-        gb[q] = (T)((vb - va) * sc * a.idx);
-    }
-    T VLb[NQ], VRb[NQ];
-    face_flux_vjp<T, SOLVER, D>(VL, VR, a.ph, gb, VLb, VRb);
-    // PLM reverse: VL = W1 + s1/2, VR = W2 - s2/2, s1 = lim(W1-W0, W2-W1),
-    // s2 = lim(W2-W1, W3-W2)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const T s1b = T(0.5) * VLb[q], s2b = T(-0.5) * VRb[q];
-        const T p1 = s1b * dp1[q], q1 = s1b * dq1[q], p2 = s2b * dp2[q], q2 = s2b * dq2[q];
-        const long long base = (long long)q * a.nfaces + fid;
-        a.C[base] = -p1;                                        // cell f-2
-        a.C[base + 9 * a.nfaces] = VLb[q] + p1 - q1 - p2;       // cell f-1
-        a.C[base + 18 * a.nfaces] = VRb[q] + q1 + p2 - q2;      // cell f
-        a.C[base + 27 * a.nfaces] = q2;                         // cell f+1
-    }
+    CellFlags f;
+    f.ghost_lo = !per && c == -1;
+    f.first = !per && c == 0;
+    f.ghost_hi = !per && c == n;
+    f.last = !per && c == n - 1;
+    return f;
 }
 
-template <typename T> struct AdjCellArgs {
-    const T *U;             // state of the linearisation
-    const T *C[3];          // contributions per axis
-    long long nfaces[3];
-    int nf[3];
-    int n[3];
-    int per[3];
-    long long ncell;
-    double gm1;
-    const double *lamp;     // lam' = dJ/dU_next
-    const double *lam1;     // stage-1 pass only
-    double *out;            // lam1 (stage-2 pass) or lamn (stage-1 pass)
-    double damp, dt;
-};
-
-template <typename T, int NDIM, int PASS>
-__global__ void __launch_bounds__(256) adj_cell_kernel(const AdjCellArgs<T> a)
+template <typename T>
+__device__ __forceinline__ T cell_item(T vl, T vr, T wm, T w0, T wp, int limiter, CellFlags fl, T &A,
+                                       T &B)
 {
-    const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (c >= a.ncell) return;
-    const int ci[3] = {(int)(c % a.n[0]), (int)((c / a.n[0]) % a.n[1]),
-                       (int)(c / ((long long)a.n[0] * a.n[1]))};
-    double vb[NQ];
+    const T sb = T(0.5) * (vl - vr);
+    T dp, dq;
+    slope_d(w0 - wm, wp - w0, limiter, dp, dq);
+    A = sb * dp;
+    B = sb * dq;
+    T E = vl + vr + A - B;
+    E = fl.first ? E - A : E;
+    E = fl.last ? E + B : E;
+    B = fl.ghost_lo ? vl : B;
+    A = fl.ghost_hi ? -vr : A;
+    return E;
+}
+
+// extended index -> cell index along an axis for the cotangent v (-1: zero)
+__device__ __forceinline__ int v_index(int m, int n, int per)
+{
+    if (per) {
+        m %= n;
+        return m < 0 ? m + n : m;
+    }
+    return (m < 0 || m >= n) ? -1 : m;
+}
+
+template <typename T, int SOLVER, int NDIM, int PASS, int TY>
+__global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T> a)
+{
+    constexpr int NT = TX * TY;
+    constexpr int H = 3;                         // LDS halo width
+    constexpr int HY = NDIM >= 2 ? H : 0;
+    constexpr int PX = TX + 2 * H;
+    constexpr int PY = TY + 2 * HY;
+    constexpr int PLANE = PX * PY;
+    constexpr int FXW = TX + 3;                  // x faces i0-1 .. i0+TX+1 per row
+    constexpr int NFX = TY * FXW;
+    constexpr int FYR = NDIM >= 2 ? TY + 3 : 0;  // y face rows j0-1 .. j0+TY+1
+    constexpr int NFY = FYR * TX;
+    constexpr int NCHX = (NFX + TX - 1) / TX;
+    constexpr int NCHUNK = NCHX + FYR;
+    constexpr int NHX = 2 * H * TY;
+    constexpr int NH = NHX + (NDIM >= 2 ? 2 * H * TX : 0);
+    constexpr int HPT = (NH + NT - 1) / NT;
+    constexpr int NCX = 2 * TY;                  // x halo cell items
+    constexpr int NCXC = (NCX + TX - 1) / TX;
+    constexpr int NCCH = NCXC + (NDIM >= 2 ? 2 : 0);
+
+    __shared__ T P[NQ * PLANE];
+    __shared__ T FX[2 * NQ * NFX];                     // [side][q][row][face]
+    __shared__ T FY[NDIM >= 2 ? 2 * NQ * NFY : 1];     // [side][q][face row][column]
+
+    const int t = threadIdx.x;
+    const int tx = t & (TX - 1);
+    const int ty = t / TX;
+    const int wave = __builtin_amdgcn_readfirstlane(ty);
+    const int lb = logical_block(blockIdx.x, a.nblocks);
+    const int tile_x = lb % a.tiles_x;
+    const int rest = lb / a.tiles_x;
+    const int tile_y = rest % a.tiles_y;
+    const int chunk = rest / a.tiles_y;
+    const int i0 = tile_x * TX, j0 = tile_y * TY;
+    const int k0 = chunk * a.kz;
+    const int k1 = min(k0 + a.kz, a.nz);
+    const int i = i0 + tx, j = j0 + ty;
+    const bool active = (i < a.nx) & (j < a.ny);
+
+    const int ri = remap_index(i, a.nx, a.per[0]);
+    const int rj = remap_index(j, a.ny, a.per[1]);
+    const long long own = (long long)rj * a.nx + ri;
+    int h_slot[HPT];
+    long long h_off[HPT];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) vb[q] = 0.0;
+    for (int m = 0; m < HPT; ++m) {
+        const int h = t + m * NT;
+        h_slot[m] = 0;
+        h_off[m] = 0;
+        if (h < NH) {
+            int lx, ly;
+            if (h < NHX) {
+                const int r = h / (2 * H), s = h % (2 * H);
+                lx = s < H ? s : TX + s;
+                ly = r + HY;
+            } else {
+                const int hy = h - NHX;
+                const int r6 = hy / TX, c = hy % TX;
+                lx = c + H;
+                ly = r6 < H ? r6 : TY + r6;
+            }
+            h_slot[m] = ly * PX + lx;
+            const int gi = remap_index(i0 + lx - H, a.nx, a.per[0]);
+            const int gj = remap_index(j0 + ly - HY, a.ny, a.per[1]);
+            h_off[m] = (long long)gj * a.nx + gi;
+        }
+    }
+    const int own_slot = (ty + HY) * PX + tx + H;
+    bool ok = true;
+
+    auto zoff = [&](int k) -> long long {
+        return (long long)remap_index(k, a.nz, a.per[2]) * a.nxy;
+    };
+    auto prim_at = [&](long long c, T *v) {
+        T u[NQ];
+        load_cell(a.U, a.ncell, c, u);
+        ok &= cons_to_prim(u, a.ph, v);
+    };
+    // flux cotangent of a face between cells ca and cb (-1: outside, zero)
+    auto face_g = [&](long long ca, long long cb, double idx, T *gb) {
 #pragma unroll
-    for (int d = 0; d < NDIM; ++d) {
-        const int n = a.n[d], x = ci[d];
-        auto add = [&](int f, int m) {
-            int e[3] = {ci[0], ci[1], ci[2]};
-            int ne[3] = {a.n[0], a.n[1], a.n[2]};
-            e[d] = f;
-            ne[d] = a.nf[d];
-            const long long fid = ((long long)e[2] * ne[1] + e[1]) * ne[0] + e[0];
-            const T *Cd = a.C[d];
+        for (int q = 0; q < NQ; ++q) {
+            double va = 0.0, vb = 0.0;
+            if (PASS == 2) {
+                const double sc = q == PSI ? a.damp : 1.0;
+                if (ca >= 0) va = a.lamp[q * a.ncell + ca] * sc;
+                if (cb >= 0) vb = a.lamp[q * a.ncell + cb] * sc;
+            } else {
+                if (ca >= 0) va = a.lam1[q * a.ncell + ca];
+                if (cb >= 0) vb = a.lam1[q * a.ncell + cb];
+            }
+            gb[q] = (T)((vb - va) * idx);
+        }
+    };
+    // face VJP from an LDS stencil w0..w3 (stride apart)
+    auto lds_face = [&](auto dir, const T *base, int stride, const T *gb, T *VLb, T *VRb) {
+        constexpr int D = decltype(dir)::value;
+        T VL[NQ], VR[NQ];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) vb[q] += (double)Cd[((long long)m * NQ + q) * a.nfaces[d] + fid];
-        };
-        // faces whose stencil position f-2+m is this cell
+        for (int q = 0; q < NQ; ++q) {
+            const T *pq = base + q * PLANE;
+            const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride];
+            VL[q] = w1 + T(0.5) * limited_slope(w1 - w0, w2 - w1, a.ph.limiter);
+            VR[q] = w2 - T(0.5) * limited_slope(w2 - w1, w3 - w2, a.ph.limiter);
+        }
+        face_flux_vjp<T, SOLVER, D>(VL, VR, a.ph, gb, VLb, VRb);
+    };
+    // cell item on the LDS stencil: faces in slots vl (VLb_{c+1}) and vr
+    // (VRb_c), overwritten with A_c and B_c; returns nothing but adds E_c
+    auto lds_cell = [&](const T *wc, int wstride, T *vl, T *vr, int fstride, CellFlags fl, T *E) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            int f = x + 2 - m;
-            if (a.per[d]) {
-                f = f >= n ? f - n : (f < 0 ? f + n : f);
-                add(f, m);
-            } else if (f >= 0 && f <= n) {
-                add(f, m);
+        for (int q = 0; q < NQ; ++q) {
+            const T *w = wc + q * PLANE;
+            T A, B;
+            const T e = cell_item(vl[q * fstride], vr[q * fstride], w[-wstride], w[0], w[wstride],
+                                  a.ph.limiter, fl, A, B);
+            vl[q * fstride] = A;
+            vr[q * fstride] = B;
+            if (E) E[q] += e;
+        }
+    };
+
+    // z partial sums carried along the march: X_kk, B_kk, VRb_{kk+1}
+    T Xz[NQ], Bz[NQ], VRz[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) Xz[q] = Bz[q] = VRz[q] = T(0);
+    const int kstart = NDIM == 3 ? k0 - 3 : k0;
+
+    for (int kk = kstart; kk < k1; ++kk) {
+        const bool out = kk >= k0;
+        const long long zk = zoff(kk);
+        if (out) {
+            // (a) primitives of plane kk into LDS
+            {
+                T w[NQ];
+                prim_at(zk + own, w);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) P[q * PLANE + own_slot] = w[q];
+            }
+#pragma unroll
+            for (int m = 0; m < HPT; ++m) {
+                if (t + m * NT < NH) {
+                    T hv[NQ];
+                    prim_at(zk + h_off[m], hv);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) P[q * PLANE + h_slot[m]] = hv[q];
+                }
+            }
+            __syncthreads();
+            // (c) x- and y-face items, 64-wide single-direction chunks
+            for (int ch = wave; ch < NCHUNK; ch += TY) {
+                T gb[NQ], VLb[NQ], VRb[NQ];
+                if (ch < NCHX) {
+                    const int it = ch * TX + tx;
+                    const bool valid = it < NFX;
+                    const int r = valid ? it / FXW : 0;
+                    const int fi = valid ? it - r * FXW : 0;
+                    const int X = i0 - 1 + fi;
+                    const long long row = zk + (long long)remap_index(j0 + r, a.ny, a.per[1]) * a.nx;
+                    const int xa = v_index(X - 1, a.nx, a.per[0]), xb = v_index(X, a.nx, a.per[0]);
+                    face_g(xa < 0 ? -1 : row + xa, xb < 0 ? -1 : row + xb, a.idx[0], gb);
+                    lds_face(std::integral_constant<int, 0>{}, &P[(r + HY) * PX + fi], 1, gb, VLb, VRb);
+                    if (valid) {
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) {
+                            FX[q * NFX + it] = VLb[q];
+                            FX[(NQ + q) * NFX + it] = VRb[q];
+                        }
+                    }
+                } else if (NDIM >= 2) {
+                    const int it = (ch - NCHX) * TX + tx;
+                    const int gi = it / TX, c = it - gi * TX;
+                    const int Y = j0 - 1 + gi;
+                    const long long col = zk + remap_index(i0 + c, a.nx, a.per[0]);
+                    const int ya = v_index(Y - 1, a.ny, a.per[1]), yb = v_index(Y, a.ny, a.per[1]);
+                    face_g(ya < 0 ? -1 : col + (long long)ya * a.nx,
+                           yb < 0 ? -1 : col + (long long)yb * a.nx, a.idx[1], gb);
+                    lds_face(std::integral_constant<int, 1>{}, &P[gi * PX + c + H], PX, gb, VLb, VRb);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        FY[q * NFY + it] = VLb[q];
+                        FY[(NQ + q) * NFY + it] = VRb[q];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // (b) z-face kk+2 and the z cell item of kk+1 (planes kk .. kk+3
+        // reloaded, they are cache resident); R starts as Wb_z of plane kk
+        T R[NQ];
+        if (NDIM == 3) {
+            T gb[NQ], VL[NQ], VR[NQ], VLb[NQ], VRb[NQ];
+            {
+                T w0[NQ], w1[NQ], w2[NQ], w3[NQ];
+                prim_at(zk + own, w0);
+                prim_at(zoff(kk + 1) + own, w1);
+                prim_at(zoff(kk + 2) + own, w2);
+                prim_at(zoff(kk + 3) + own, w3);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    VL[q] = w1[q] + T(0.5) * limited_slope(w1[q] - w0[q], w2[q] - w1[q], a.ph.limiter);
+                    VR[q] = w2[q] - T(0.5) * limited_slope(w2[q] - w1[q], w3[q] - w2[q], a.ph.limiter);
+                }
+            }
+            const int za = v_index(kk + 1, a.nz, a.per[2]), zb = v_index(kk + 2, a.nz, a.per[2]);
+            face_g(za < 0 ? -1 : za * a.nxy + own, zb < 0 ? -1 : zb * a.nxy + own, a.idx[2], gb);
+            face_flux_vjp<T, SOLVER, 2>(VL, VR, a.ph, gb, VLb, VRb);
+            const CellFlags fl = cell_flags(kk + 1, a.nz, a.per[2]);
+            T w0[NQ], w1[NQ], w2[NQ];
+            prim_at(zk + own, w0);
+            prim_at(zoff(kk + 1) + own, w1);
+            prim_at(zoff(kk + 2) + own, w2);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                T A, B;
+                const T E = cell_item(VLb[q], VRz[q], w0[q], w1[q], w2[q], a.ph.limiter, fl, A, B);
+                R[q] = Xz[q] - A;
+                Xz[q] = E + Bz[q];
+                Bz[q] = B;
+                VRz[q] = VRb[q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) R[q] = T(0);
+        }
+        if (!out) continue;
+        // (d) cell items: own cells (x and y), then the halo cells
+        {
+            const int fo = ty * FXW + tx + 1;  // slot of face i (own cell's lower x face)
+            lds_cell(&P[own_slot], 1, &FX[fo + 1], &FX[NQ * NFX + fo], NFX, cell_flags(i, a.nx, a.per[0]),
+                     R);
+            if (NDIM >= 2) {
+                const int go = (ty + 1) * TX + tx;  // slot of face j (own cell's lower y face)
+                lds_cell(&P[own_slot], PX, &FY[go + TX], &FY[NQ * NFY + go], NFY,
+                         cell_flags(j, a.ny, a.per[1]), R);
             }
         }
-        if (!a.per[d]) {
-            // ghost positions clamped onto the boundary cells
-            if (x == 0) {
-                add(0, 0);
-                add(0, 1);
-                add(1, 0);
+        for (int hc = TY - 1 - wave; hc < NCCH; hc += TY) {
+            if (hc < NCXC) {
+                const int it = hc * TX + tx;
+                if (it < NCX) {
+                    const int r = it >> 1, side = it & 1;
+                    const int fi = side ? TX + 1 : 0;      // face slot of the cell's lower face
+                    const int X = i0 - 1 + fi;
+                    const int fo = r * FXW + fi;
+                    lds_cell(&P[(r + HY) * PX + fi + H - 1], 1, &FX[fo + 1], &FX[NQ * NFX + fo], NFX,
+                             cell_flags(X, a.nx, a.per[0]), nullptr);
+                }
+            } else if (NDIM >= 2) {
+                const int side = hc - NCXC;
+                const int gi = side ? TY + 1 : 0;          // face row of the cell's lower face
+                const int Y = j0 - 1 + gi;
+                const int go = gi * TX + tx;
+                lds_cell(&P[(gi + HY - 1) * PX + tx + H], PX, &FY[go + TX], &FY[NQ * NFY + go], NFY,
+                         cell_flags(Y, a.ny, a.per[1]), nullptr);
             }
-            if (x == n - 1) {
-                add(n, 2);
-                add(n, 3);
-                add(n - 1, 3);
+        }
+        __syncthreads();
+        // (f) neighbours' A and B, FP64 sum over axes, transpose, combine
+        if (active) {
+            double wb[NQ];
+            {
+                const int fo = ty * FXW + tx + 1;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    double r = (double)R[q] + (double)(FX[(NQ + q) * NFX + fo - 1] - FX[q * NFX + fo + 2]);
+                    if (NDIM >= 2) {
+                        const int go = (ty + 1) * TX + tx;
+                        r += (double)(FY[(NQ + q) * NFY + go - TX] - FY[q * NFY + go + 2 * TX]);
+                    }
+                    wb[q] = r;
+                }
+            }
+            const long long c = zk + own;
+            double u[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) u[q] = (double)a.U[q * a.ncell + c];
+            const double ir = 1.0 / u[RHO];
+            const double v[3] = {u[MX] * ir, u[MY] * ir, u[MZ] * ir};
+            const double vsq = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+            double r[NQ];
+            r[RHO] = wb[RHO] - (v[0] * wb[VX] + v[1] * wb[VY] + v[2] * wb[VZ]) * ir +
+                     a.gm1 * 0.5 * vsq * wb[PRS];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                r[MX + k] = wb[VX + k] * ir - a.gm1 * v[k] * wb[PRS];
+                r[BX + k] = wb[BX + k] - a.gm1 * u[BX + k] * wb[PRS];
+            }
+            r[ENG] = a.gm1 * wb[PRS];
+            r[PSI] = wb[PSI];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const double mu = a.lamp[q * a.ncell + c] * (q == PSI ? a.damp : 1.0);
+                double o;
+                if (PASS == 2)
+                    o = 0.5 * mu + 0.5 * a.dt * r[q];
+                else
+                    o = 0.5 * mu + a.lam1[q * a.ncell + c] + a.dt * r[q];
+                a.out[q * a.ncell + c] = o;
             }
         }
     }
-    // transpose of the conserved -> primitive Jacobian (FP64)
-    double u[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) u[q] = (double)a.U[q * a.ncell + c];
-    const double ir = 1.0 / u[RHO];
-    const double v[3] = {u[MX] * ir, u[MY] * ir, u[MZ] * ir};
-    const double vsq = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    double r[NQ];
-    r[RHO] = vb[RHO] - (v[0] * vb[VX] + v[1] * vb[VY] + v[2] * vb[VZ]) * ir + a.gm1 * 0.5 * vsq * vb[PRS];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        r[MX + k] = vb[VX + k] * ir - a.gm1 * v[k] * vb[PRS];
-        r[BX + k] = vb[BX + k] - a.gm1 * u[BX + k] * vb[PRS];
-    }
-    r[ENG] = a.gm1 * vb[PRS];
-    r[PSI] = vb[PSI];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const double mu = a.lamp[q * a.ncell + c] * (q == PSI ? a.damp : 1.0);
-        double o;
-        if (PASS == 2)
-            o = 0.5 * mu + 0.5 * a.dt * r[q];
-        else
-            o = 0.5 * mu + a.lam1[q * a.ncell + c] + a.dt * r[q];
-        a.out[q * a.ncell + c] = o;
-    }
+    if (!ok) atomicOr(a.flag, 1);
 }
 
 } // namespace mhd

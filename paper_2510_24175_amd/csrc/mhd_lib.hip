@@ -31,9 +31,6 @@ struct mhd_ctx {
     int *flag = nullptr;         // device non-physical flag
     double *host_res = nullptr;  // pinned NPART doubles + flag word
     double *lam1 = nullptr;      // adjoint: FP64 stage cotangent
-    void *adjC[3] = {nullptr, nullptr, nullptr}; // adjoint: per-face contributions
-    long long nfaces[3] = {0, 0, 0};
-    int nf[3] = {1, 1, 1};
     bool have_step = false;
     double cell_volume = 1.0;
     double dx[3] = {1, 1, 1};
@@ -59,13 +56,13 @@ mhd_status fail(mhd_ctx *ctx, mhd_status st, const std::string &msg)
             return fail((ctx), MHD_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-// Stage tile rows per workgroup (one wave per row).  FP32: 6 rows, so two
-// workgroups (12 waves) share a compute unit at the 168-VGPR budget and
-// fill each other's barrier waits, with 20 face rounds per 384 cells per
-// plane.  FP64 (register bound at one wave per SIMD): 4 rows.  1D: 1 row.
+// Stage tile rows per workgroup (one wave per row).  FP32: 4 rows, three
+// workgroups (12 waves) per compute unit at the 168-VGPR budget; measured
+// faster than 6 rows (two workgroups of 6 waves) by a third.  FP64 (register
+// bound at one wave per SIMD): 4 rows.  1D: 1 row.
 template <typename T, int NDIM> constexpr int tile_rows()
 {
-    return NDIM == 1 ? 1 : (sizeof(T) == 4 ? 6 : 4);
+    return NDIM == 1 ? 1 : 4;
 }
 
 struct Launch {
@@ -173,51 +170,48 @@ mhd_status launch_step_nd(mhd_ctx *ctx, const void *un, void *unext, void *u1, d
     }
 }
 
-template <typename T, int SOLVER, int D>
-void launch_adj_face(mhd_ctx *ctx, const T *U, const double *lam, double psi_scale, double ch)
+// Adjoint tile rows per workgroup: FP32 8 rows (one 512-thread workgroup
+// per compute unit, 124.6 KB of LDS, y-face halo overhead 3/8); FP64 4 rows
+// (153.5 KB of LDS); 1D: 1 row.
+template <typename T, int NDIM> constexpr int adj_tile_rows()
 {
-    AdjArgs<T> a;
-    a.U = U;
-    a.lam = lam;
-    a.psi_scale = psi_scale;
-    a.C = (T *)ctx->adjC[D];
-    a.flag = ctx->flag;
-    for (int d = 0; d < 3; ++d) {
-        a.n[d] = (int)ctx->n[d];
-        a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
-    }
-    a.nxy = ctx->n[0] * ctx->n[1];
-    a.ncell = ctx->ncell;
-    a.nf = ctx->nf[D];
-    a.nfaces = ctx->nfaces[D];
-    a.idx = 1.0 / ctx->dx[D];
-    a.ph = make_phys<T>(ctx, ch);
-    const long long nb = (a.nfaces + 255) / 256;
-    hipLaunchKernelGGL((adj_face_kernel<T, SOLVER, D>), dim3((unsigned)nb), dim3(256), 0, ctx->stream, a);
+    return NDIM == 1 ? 1 : (sizeof(T) == 4 ? 8 : 4);
 }
 
-template <typename T, int NDIM, int PASS>
-void launch_adj_cell(mhd_ctx *ctx, const T *U, const double *lamp, const double *lam1, double *out,
-                     double dt, double damp)
+template <typename T, int SOLVER, int NDIM, int PASS>
+mhd_status launch_adj_stage(mhd_ctx *ctx, const T *U, const double *lamp, const double *lam1,
+                            double *out, double dt, double ch, double damp)
 {
-    AdjCellArgs<T> a;
+    constexpr int TY = adj_tile_rows<T, NDIM>();
+    const Launch L = plan_stage(ctx, TY);
+    AdjStageArgs<T> a;
     a.U = U;
-    for (int d = 0; d < 3; ++d) {
-        a.C[d] = (const T *)ctx->adjC[d];
-        a.nfaces[d] = ctx->nfaces[d];
-        a.nf[d] = ctx->nf[d];
-        a.n[d] = (int)ctx->n[d];
-        a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
-    }
-    a.ncell = ctx->ncell;
-    a.gm1 = ctx->cfg.gamma - 1.0;
     a.lamp = lamp;
     a.lam1 = lam1;
     a.out = out;
-    a.damp = damp;
+    a.flag = ctx->flag;
+    a.nx = (int)ctx->n[0];
+    a.ny = (int)ctx->n[1];
+    a.nz = (int)ctx->n[2];
+    a.nxy = ctx->n[0] * ctx->n[1];
+    a.ncell = ctx->ncell;
+    for (int d = 0; d < 3; ++d) {
+        a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
+        a.idx[d] = 1.0 / ctx->dx[d];
+    }
+    a.kz = L.kz;
+    a.tiles_x = L.tiles_x;
+    a.tiles_y = L.tiles_y;
+    a.chunks = L.chunks;
+    a.nblocks = L.nblocks;
     a.dt = dt;
-    const long long nb = (ctx->ncell + 255) / 256;
-    hipLaunchKernelGGL((adj_cell_kernel<T, NDIM, PASS>), dim3((unsigned)nb), dim3(256), 0, ctx->stream, a);
+    a.damp = damp;
+    a.gm1 = ctx->cfg.gamma - 1.0;
+    a.ph = make_phys<T>(ctx, ch);
+    hipLaunchKernelGGL((adj_stage_kernel<T, SOLVER, NDIM, PASS, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+                       ctx->stream, a);
+    HIP_TRY(ctx, hipGetLastError());
+    return MHD_OK;
 }
 
 template <typename T, int SOLVER, int NDIM>
@@ -260,19 +254,11 @@ mhd_status launch_adjoint(mhd_ctx *ctx, const T *un, const T *u1, const double *
         u1 = (const T *)ctx->u1_scratch;
     }
     // stage-2 pass: lam1 = mu/2 + (dt/2) J_L(U1)^T mu, mu = D lam'
-    launch_adj_face<T, SOLVER, 0>(ctx, u1, lamp, damp, ch);
-    if (NDIM >= 2) launch_adj_face<T, SOLVER, 1>(ctx, u1, lamp, damp, ch);
-    if (NDIM >= 3) launch_adj_face<T, SOLVER, 2>(ctx, u1, lamp, damp, ch);
-    HIP_TRY(ctx, hipGetLastError());
-    launch_adj_cell<T, NDIM, 2>(ctx, u1, lamp, nullptr, ctx->lam1, dt, damp);
-    HIP_TRY(ctx, hipGetLastError());
+    mhd_status st = launch_adj_stage<T, SOLVER, NDIM, 2>(ctx, u1, lamp, nullptr, ctx->lam1, dt, ch, damp);
+    if (st != MHD_OK) return st;
     // stage-1 pass: lamn = mu/2 + lam1 + dt J_L(Un)^T lam1
-    launch_adj_face<T, SOLVER, 0>(ctx, un, ctx->lam1, 1.0, ch);
-    if (NDIM >= 2) launch_adj_face<T, SOLVER, 1>(ctx, un, ctx->lam1, 1.0, ch);
-    if (NDIM >= 3) launch_adj_face<T, SOLVER, 2>(ctx, un, ctx->lam1, 1.0, ch);
-    HIP_TRY(ctx, hipGetLastError());
-    launch_adj_cell<T, NDIM, 1>(ctx, un, lamp, ctx->lam1, lamn, dt, damp);
-    HIP_TRY(ctx, hipGetLastError());
+    st = launch_adj_stage<T, SOLVER, NDIM, 1>(ctx, un, lamp, ctx->lam1, lamn, dt, ch, damp);
+    if (st != MHD_OK) return st;
     return MHD_OK;
 }
 
@@ -383,8 +369,6 @@ void free_ctx(mhd_ctx *ctx)
     if (ctx->flag) (void)hipFree(ctx->flag);
     if (ctx->host_res) (void)hipHostFree(ctx->host_res);
     if (ctx->lam1) (void)hipFree(ctx->lam1);
-    for (int d = 0; d < 3; ++d)
-        if (ctx->adjC[d]) (void)hipFree(ctx->adjC[d]);
     delete ctx;
 }
 
@@ -473,7 +457,10 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
         if (d < cfg->ndim) ctx->cell_volume *= ctx->dx[d];
     }
     ctx->elem = cfg->dtype == MHD_F32 ? 4 : 8;
-    const int ty = cfg->ndim == 1 ? 1 : (cfg->dtype == MHD_F32 ? 6 : 4);
+    // partials capacity: the forward stage grid (the CFL kernel uses at most
+    // CFL_MAX_BLOCKS); the adjoint writes no partials
+    const int ty = cfg->ndim == 1 ? tile_rows<float, 1>()
+                 : (cfg->dtype == MHD_F32 ? tile_rows<float, 3>() : tile_rows<double, 3>());
     const Launch L = plan_stage(ctx, ty);
     ctx->part_cap = std::max(L.nblocks, CFL_MAX_BLOCKS);
     hipError_t e = hipMalloc(&ctx->u1_scratch, (size_t)NQ * ctx->ncell * ctx->elem);
@@ -481,15 +468,8 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->result, NPART * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->flag, sizeof(int));
     if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->host_res, (NPART + 1) * sizeof(double));
-    for (int d = 0; d < 3; ++d) {
-        ctx->nf[d] = d < cfg->ndim ? (int)(cfg->bc[d][0] == MHD_PERIODIC ? cfg->n[d] : cfg->n[d] + 1) : 1;
-        ctx->nfaces[d] = ctx->ncell / cfg->n[d] * ctx->nf[d];
-    }
-    if (e == hipSuccess && (cfg->flags & MHD_FLAG_ADJOINT)) {
+    if (e == hipSuccess && (cfg->flags & MHD_FLAG_ADJOINT))
         e = hipMalloc((void **)&ctx->lam1, (size_t)NQ * ctx->ncell * sizeof(double));
-        for (int d = 0; d < cfg->ndim && e == hipSuccess; ++d)
-            e = hipMalloc(&ctx->adjC[d], (size_t)4 * NQ * ctx->nfaces[d] * ctx->elem);
-    }
     if (e == hipSuccess) e = hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
