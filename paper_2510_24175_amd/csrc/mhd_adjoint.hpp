@@ -31,25 +31,35 @@ template <typename T> struct DBar {
     T irho = 0, bsq = 0, E = 0, pt = 0, vb = 0;
 };
 
-// reverse of rstate_finish: derived (irho, bsq, E, pt, vb) -> primaries
+// reverse of rstate_prepare: cotangents of (irho, bsq, pt) -> primaries
 template <typename T>
-__device__ __forceinline__ void finish_rev(const RState<T> &s, const Phys<T> &ph, const DBar<T> &d,
-                                           RBar<T> &b)
+__device__ __forceinline__ void prepare_rev(const RState<T> &s, const DBar<T> &d, RBar<T> &b)
 {
-    b.p += d.E * ph.inv_gm1 + d.pt;
-    const T ke = s.u * s.u + s.v1 * s.v1 + s.v2 * s.v2;
-    b.rho += T(0.5) * ke * d.E - s.irho * s.irho * d.irho;
-    const T keb = T(0.5) * s.rho * d.E;
-    b.u += T(2) * s.u * keb + s.bn * d.vb;
-    b.v1 += T(2) * s.v1 * keb + s.b1 * d.vb;
-    b.v2 += T(2) * s.v2 * keb + s.b2 * d.vb;
-    const T bsqb = d.bsq + T(0.5) * d.E + T(0.5) * d.pt;
-    b.bn += T(2) * s.bn * bsqb + s.u * d.vb;
-    b.b1 += T(2) * s.b1 * bsqb + s.v1 * d.vb;
-    b.b2 += T(2) * s.b2 * bsqb + s.v2 * d.vb;
+    b.p += d.pt;
+    b.rho -= s.irho * s.irho * d.irho;
+    const T bsqb = d.bsq + T(0.5) * d.pt;
+    b.bn += T(2) * s.bn * bsqb;
+    b.b1 += T(2) * s.b1 * bsqb;
+    b.b2 += T(2) * s.b2 * bsqb;
 }
 
-// reverse of rstate_flux (physical flux f and conserved vector c)
+// reverse of rstate_energy: cotangents of (E, v.B) -> primaries
+template <typename T>
+__device__ __forceinline__ void energy_rev(const RState<T> &s, const Phys<T> &ph, T Eb, T vbb, RBar<T> &b)
+{
+    b.p += Eb * ph.inv_gm1;
+    b.rho += T(0.5) * (s.u * s.u + s.v1 * s.v1 + s.v2 * s.v2) * Eb;
+    const T rE = s.rho * Eb;
+    b.u += s.u * rE + s.bn * vbb;
+    b.v1 += s.v1 * rE + s.b1 * vbb;
+    b.v2 += s.v2 * rE + s.b2 * vbb;
+    b.bn += s.bn * Eb + s.u * vbb;
+    b.b1 += s.b1 * Eb + s.v1 * vbb;
+    b.b2 += s.b2 * Eb + s.v2 * vbb;
+}
+
+// reverse of rstate_flux (physical flux f and conserved vector c); the
+// cotangents of E, v.B and pt go to d
 template <typename T>
 __device__ __forceinline__ void flux_rev(const RState<T> &s, const T *fb, const T *cb, RBar<T> &b,
                                          DBar<T> &d)
@@ -69,21 +79,32 @@ __device__ __forceinline__ void flux_rev(const RState<T> &s, const T *fb, const 
     b.rho += cb[0] + s.v1 * cb[2] + s.v2 * cb[3] + mub * s.u;
 }
 
-// reverse of rstate_fast: c = sqrt((a2 + b2 + sqrt(disc))/2)
+// fast speed of a prepared state (same arithmetic as fast_speed), with the
+// root of the discriminant that its reverse reuses
 template <typename T>
-__device__ __forceinline__ void fast_rev(const RState<T> &s, const Phys<T> &ph, T c, T cbar, RBar<T> &b,
-                                         DBar<T> &d)
+__device__ __forceinline__ T fast_fwd(const RState<T> &s, const Phys<T> &ph, T &sd)
+{
+    const T a2 = ph.gamma * s.p * s.irho;
+    const T b2 = s.bsq * s.irho;
+    const T bn2 = (s.bn * s.bn) * s.irho;
+    const T dab = a2 - b2;
+    T disc = dab * dab + T(4) * a2 * (b2 - bn2);
+    disc = Num<T>::max(disc, T(0));
+    sd = Num<T>::sqrt(disc);
+    return Num<T>::sqrt(T(0.5) * (a2 + b2 + sd));
+}
+
+// reverse of fast_fwd: c = sqrt((a2 + b2 + sd)/2), sd = sqrt(max(disc, 0))
+template <typename T>
+__device__ __forceinline__ void fast_rev(const RState<T> &s, const Phys<T> &ph, T c, T sd, T cbar,
+                                         RBar<T> &b, DBar<T> &d)
 {
     const T a2 = ph.gamma * s.p * s.irho, b2 = s.bsq * s.irho, bn2 = s.bn * s.bn;
     const T n2 = bn2 * s.irho;
     const T dab = a2 - b2;
-    const T disc0 = dab * dab + T(4) * a2 * (b2 - n2);
-    const bool dpos = disc0 > T(0);
-    const T sd = Num<T>::sqrt(dpos ? disc0 : T(0));
     const T c2b = cbar * T(0.5) * Num<T>::rcp(c);
     T a2b = T(0.5) * c2b, b2b = T(0.5) * c2b;
-    const T sdb = T(0.5) * c2b;
-    const T discb = (dpos && sd > T(0)) ? sdb * T(0.5) * Num<T>::rcp(sd) : T(0);
+    const T discb = sd > T(0) ? T(0.25) * c2b * Num<T>::rcp(sd) : T(0);
     const T dabb = T(2) * dab * discb;
     a2b += dabb + T(4) * (b2 - n2) * discb;
     b2b += -dabb + T(4) * a2 * discb;
@@ -94,15 +115,21 @@ __device__ __forceinline__ void fast_rev(const RState<T> &s, const Phys<T> &ph, 
     b.bn += T(2) * s.bn * s.irho * n2b;
 }
 
+// HLL VJP on prepared states; their energies are formed here (as hll_flux
+// does) and reversed here, so Ld and Rd return irho, bsq and pt cotangents
 template <typename T>
 __device__ __forceinline__ void hll_vjp(const RState<T> &L, const RState<T> &R, const Phys<T> &ph,
                                         const T *Fb, RBar<T> &Lb, RBar<T> &Rb, DBar<T> &Ld,
                                         DBar<T> &Rd, T &bnb)
 {
+    RState<T> Le = L, Re = R;
+    rstate_energy(Le, ph);
+    rstate_energy(Re, ph);
     T FL[8], UL[8], FR[8], UR[8];
-    rstate_flux(L, FL, UL);
-    rstate_flux(R, FR, UR);
-    const T cL = rstate_fast(L, ph), cR = rstate_fast(R, ph);
+    rstate_flux(Le, FL, UL);
+    rstate_flux(Re, FR, UR);
+    T sdL, sdR;
+    const T cL = fast_fwd(L, ph, sdL), cR = fast_fwd(R, ph, sdR);
     const T xL = L.u - cL, xR = R.u - cR, yL = L.u + cL, yR = R.u + cR;
     const bool selx = xL <= xR, sely = yL >= yR;
     const T xm = selx ? xL : xR, ym = sely ? yL : yR;
@@ -126,24 +153,28 @@ __device__ __forceinline__ void hll_vjp(const RState<T> &L, const RState<T> &R, 
     T cLb = 0, cRb = 0;
     if (selx) { Lb.u += xmb; cLb -= xmb; } else { Rb.u += xmb; cRb -= xmb; }
     if (sely) { Lb.u += ymb; cLb += ymb; } else { Rb.u += ymb; cRb += ymb; }
-    flux_rev(L, FLb, ULb, Lb, Ld);
-    flux_rev(R, FRb, URb, Rb, Rd);
-    fast_rev(L, ph, cL, cLb, Lb, Ld);
-    fast_rev(R, ph, cR, cRb, Rb, Rd);
+    flux_rev(Le, FLb, ULb, Lb, Ld);
+    flux_rev(Re, FRb, URb, Rb, Rd);
+    energy_rev(Le, ph, Ld.E, Ld.vb, Lb);
+    energy_rev(Re, ph, Rd.E, Rd.vb, Rb);
+    fast_rev(L, ph, cL, sdL, cLb, Lb, Ld);
+    fast_rev(R, ph, cR, sdR, cRb, Rb, Rd);
     (void)bnb;
 }
 
-// single-star state with the intermediates its reverse needs
+// single-star state without its energy (formed for the picked side only),
+// with the intermediates its reverse needs
 template <typename T> struct StarT {
-    T su, sd, isd, m, rho, mm, D, iD, cv, cb, v1, v2, b1, b2, vb, Enum, E, isq, sq;
+    T su, sd, isd, m, rho, mm, D, iD, cv, cb, v1, v2, b1, b2, isq, sq;
     bool deg;
 };
+// cotangents of a single-star state's outputs and of S - u and 1/(S - S_M)
 template <typename T> struct StarB {
-    T rho = 0, v1 = 0, v2 = 0, b1 = 0, b2 = 0, E = 0, vb = 0, sq = 0, isq = 0;
+    T rho = 0, v1 = 0, v2 = 0, b1 = 0, b2 = 0, sq = 0, isq = 0, su = 0, isd = 0;
 };
 
 template <typename T>
-__device__ __forceinline__ void star_fwd(const RState<T> &s, T S, T sM, T pts, StarT<T> &o)
+__device__ __forceinline__ void star_fwd(const RState<T> &s, T S, T sM, StarT<T> &o)
 {
     o.su = S - s.u;
     o.sd = S - sM;
@@ -161,38 +192,18 @@ __device__ __forceinline__ void star_fwd(const RState<T> &s, T S, T sM, T pts, S
     o.v2 = o.deg ? s.v2 : s.v2 - s.b2 * o.cv;
     o.b1 = o.deg ? s.b1 : s.b1 * o.cb;
     o.b2 = o.deg ? s.b2 : s.b2 * o.cb;
-    o.vb = sM * s.bn + o.v1 * o.b1 + o.v2 * o.b2;
-    o.Enum = o.su * s.E - s.pt * s.u + pts * sM + s.bn * (s.vb - o.vb);
-    o.E = o.Enum * o.isd;
     o.isq = Num<T>::rsqrt(o.rho);
     o.sq = o.rho * o.isq;
 }
 
 template <typename T>
-__device__ __forceinline__ void star_rev(const RState<T> &s, T sM, T pts, const StarT<T> &o, StarB<T> ob,
-                                         RBar<T> &sb, DBar<T> &sd_, T &Sb, T &sMb, T &ptsb, T &bnb)
+__device__ __forceinline__ void star_rev(const RState<T> &s, T sM, const StarT<T> &o, const StarB<T> &ob,
+                                         RBar<T> &sb, T &Sb, T &sMb, T &bnb)
 {
-    ob.rho += ob.sq * o.isq;
-    ob.isq += ob.sq * o.rho;
-    ob.rho += ob.isq * T(-0.5) * o.isq * o.isq * o.isq;
-    const T Enumb = ob.E * o.isd;
-    T isdb = ob.E * o.Enum;
-    T sub = Enumb * s.E;
-    sd_.E += Enumb * o.su;
-    sd_.pt -= Enumb * s.u;
-    sb.u -= Enumb * s.pt;
-    ptsb += Enumb * sM;
-    sMb += Enumb * pts;
-    bnb += Enumb * (s.vb - o.vb);
-    sd_.vb += Enumb * s.bn;
-    ob.vb -= Enumb * s.bn;
-    sMb += ob.vb * s.bn;
-    bnb += ob.vb * sM;
-    ob.v1 += ob.vb * o.b1;
-    ob.b1 += ob.vb * o.v1;
-    ob.v2 += ob.vb * o.b2;
-    ob.b2 += ob.vb * o.v2;
-    T mb = 0, sdb = 0;
+    // sq = rho isq, isq = rho^(-1/2)
+    const T isqb = ob.isq + ob.sq * o.rho;
+    const T rhob = ob.rho + ob.sq * o.isq - T(0.5) * o.isq * o.isq * o.isq * isqb;
+    T mb = 0, sdb = 0, sub = ob.su, isdb = ob.isd;
     sb.v1 += ob.v1;
     sb.v2 += ob.v2;
     if (o.deg) {
@@ -218,8 +229,8 @@ __device__ __forceinline__ void star_rev(const RState<T> &s, T sM, T pts, const 
         mb += Db * o.sd;
         sdb += Db * o.m;
     }
-    mb += ob.rho * o.isd;
-    isdb += ob.rho * o.m;
+    mb += rhob * o.isd;
+    isdb += rhob * o.m;
     sdb += -o.isd * o.isd * isdb;
     sb.rho += mb * o.su;
     sub += mb * s.rho;
@@ -240,33 +251,19 @@ __device__ __forceinline__ RState<T> pick_state(bool c, const RState<T> &a, cons
     o.pt = c ? a.pt : b.pt; o.vb = c ? a.vb : b.vb;
     return o;
 }
-template <typename T>
-__device__ __forceinline__ void add_picked(bool c, const RBar<T> &x, const DBar<T> &y, RBar<T> &La,
-                                           DBar<T> &Ld, RBar<T> &Ra, DBar<T> &Rd)
-{
-    const T z = T(0);
-    La.rho += c ? x.rho : z; Ra.rho += c ? z : x.rho;
-    La.u += c ? x.u : z; Ra.u += c ? z : x.u;
-    La.v1 += c ? x.v1 : z; Ra.v1 += c ? z : x.v1;
-    La.v2 += c ? x.v2 : z; Ra.v2 += c ? z : x.v2;
-    La.p += c ? x.p : z; Ra.p += c ? z : x.p;
-    La.bn += c ? x.bn : z; Ra.bn += c ? z : x.bn;
-    La.b1 += c ? x.b1 : z; Ra.b1 += c ? z : x.b1;
-    La.b2 += c ? x.b2 : z; Ra.b2 += c ? z : x.b2;
-    Ld.irho += c ? y.irho : z; Rd.irho += c ? z : y.irho;
-    Ld.bsq += c ? y.bsq : z; Rd.bsq += c ? z : y.bsq;
-    Ld.E += c ? y.E : z; Rd.E += c ? z : y.E;
-    Ld.pt += c ? y.pt : z; Rd.pt += c ? z : y.pt;
-    Ld.vb += c ? y.vb : z; Rd.vb += c ? z : y.vb;
-}
-
+// HLLD VJP on prepared states (Miyoshi & Kusano 2005, same arithmetic and
+// decisions as hlld_flux): the forward is recomputed, then reversed
+// statement by statement.  The side the flux is taken from (left of the
+// contact when S_M >= 0) alone carries energies; its cotangents are added to
+// the left or right accumulators with 0/1 weights.
 template <typename T>
 __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R, const Phys<T> &ph,
                                          const T *Fb, RBar<T> &Lb, RBar<T> &Rb, DBar<T> &Ld,
                                          DBar<T> &Rd, T &bnb)
 {
-    // ---- forward (same arithmetic as hlld_flux) ----
-    const T cL = rstate_fast(L, ph), cR = rstate_fast(R, ph);
+    // ---- forward ----
+    T sdL, sdR;
+    const T cL = fast_fwd(L, ph, sdL), cR = fast_fwd(R, ph, sdR);
     const T xL = L.u - cL, xR = R.u - cR, yL = L.u + cL, yR = R.u + cR;
     const bool selx = xL <= xR, sely = yL >= yR;
     const T sL = selx ? xL : xR, sR = sely ? yL : yR;
@@ -279,8 +276,8 @@ __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R,
     const T pts = npt * idm;
     const T bn = L.bn;
     StarT<T> sl, sr;
-    star_fwd(L, sL, sM, pts, sl);
-    star_fwd(R, sR, sM, pts, sr);
+    star_fwd(L, sL, sM, sl);
+    star_fwd(R, sR, sM, sr);
     const T sgn = bn >= T(0) ? T(1) : T(-1);
     const T abn = Num<T>::abs(bn);
     const T ssL = sM - abn * sl.isq;
@@ -295,15 +292,20 @@ __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R,
     const T b1 = N1 * iden, b2 = N2 * iden;
     const T vbss = sM * bn + v1 * b1 + v2 * b2;
     const bool left = sM >= T(0);
-    const RState<T> S = pick_state(left, L, R);
+    const T wl = left ? T(1) : T(0), wr = T(1) - wl;
+    RState<T> S = pick_state(left, L, R);
+    rstate_energy(S, ph);
     StarT<T> st;
     st.su = left ? sl.su : sr.su; st.sd = left ? sl.sd : sr.sd; st.isd = left ? sl.isd : sr.isd;
     st.m = left ? sl.m : sr.m; st.rho = left ? sl.rho : sr.rho; st.mm = left ? sl.mm : sr.mm;
     st.D = left ? sl.D : sr.D; st.iD = left ? sl.iD : sr.iD; st.cv = left ? sl.cv : sr.cv;
     st.cb = left ? sl.cb : sr.cb; st.v1 = left ? sl.v1 : sr.v1; st.v2 = left ? sl.v2 : sr.v2;
-    st.b1 = left ? sl.b1 : sr.b1; st.b2 = left ? sl.b2 : sr.b2; st.vb = left ? sl.vb : sr.vb;
-    st.Enum = left ? sl.Enum : sr.Enum; st.E = left ? sl.E : sr.E; st.isq = left ? sl.isq : sr.isq;
-    st.sq = left ? sl.sq : sr.sq; st.deg = left ? sl.deg : sr.deg;
+    st.b1 = left ? sl.b1 : sr.b1; st.b2 = left ? sl.b2 : sr.b2;
+    st.isq = left ? sl.isq : sr.isq; st.sq = left ? sl.sq : sr.sq; st.deg = left ? sl.deg : sr.deg;
+    // single-star energy of the picked side
+    const T vbs = sM * bn + st.v1 * st.b1 + st.v2 * st.b2;
+    const T Enum = st.su * S.E - S.pt * S.u + pts * sM + bn * (S.vb - vbs);
+    const T Es = Enum * st.isd;
     const T s_out = left ? sL : sR;
     const T s_in = left ? ssL : ssR;
     const bool outer = left ? (sL >= T(0)) : (sR <= T(0));
@@ -311,58 +313,53 @@ __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R,
     const T a1 = outer ? T(0) : s_out;
     const T a2 = (outer || !dbl) ? T(0) : s_in;
     const T sig = left ? T(-1) : T(1);
-    const T Ess = st.E + sig * st.sq * (st.vb - vbss) * sgn;
+    const T Ess = Es + sig * st.sq * (vbs - vbss) * sgn;
     T f[8], u[8];
     rstate_flux(S, f, u);
-    const T us[8] = {st.rho, st.rho * sM, st.rho * st.v1, st.rho * st.v2, st.E, bn, st.b1, st.b2};
+    const T us[8] = {st.rho, st.rho * sM, st.rho * st.v1, st.rho * st.v2, Es, bn, st.b1, st.b2};
     const T uss[8] = {st.rho, st.rho * sM, st.rho * v1, st.rho * v2, Ess, bn, b1, b2};
 
     // ---- reverse ----
+    // F = f + a1 (us - u) + a2 (uss - us)
     T ub[8];
     T a1b = 0, a2b = 0;
-    StarB<T> stb;
-    T sMb = 0, v1b = 0, v2b = 0, b1b = 0, b2b = 0, Essb = 0, vbssb = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         ub[k] = -a1 * Fb[k];
         a1b += Fb[k] * (us[k] - u[k]);
         a2b += Fb[k] * (uss[k] - us[k]);
     }
-    // uss = (rho*, rho* sM, rho* v1**, rho* v2**, E**, bn, b1**, b2**), weight a2
+    StarB<T> stb;
+    T sMb, v1b, v2b, b1b, b2b, Essb, Esb;
     {
-        T w[8];
+        // uss with weight a2, us with weight a1 - a2
+        T w[8], x[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) w[k] = a2 * Fb[k];
-        stb.rho += w[0] + w[1] * sM + w[2] * v1 + w[3] * v2;
-        sMb += w[1] * st.rho;
-        v1b += w[2] * st.rho;
-        v2b += w[3] * st.rho;
-        Essb += w[4];
-        bnb += w[5];
-        b1b += w[6];
-        b2b += w[7];
-    }
-    // us, weight a1 - a2
-    {
-        T w[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) w[k] = (a1 - a2) * Fb[k];
-        stb.rho += w[0] + w[1] * sM + w[2] * st.v1 + w[3] * st.v2;
-        sMb += w[1] * st.rho;
-        stb.v1 += w[2] * st.rho;
-        stb.v2 += w[3] * st.rho;
-        stb.E += w[4];
-        bnb += w[5];
-        stb.b1 += w[6];
-        stb.b2 += w[7];
+        for (int k = 0; k < 8; ++k) {
+            w[k] = a2 * Fb[k];
+            x[k] = (a1 - a2) * Fb[k];
+        }
+        stb.rho = w[0] + w[1] * sM + w[2] * v1 + w[3] * v2 + x[0] + x[1] * sM + x[2] * st.v1 + x[3] * st.v2;
+        sMb = (w[1] + x[1]) * st.rho;
+        v1b = w[2] * st.rho;
+        v2b = w[3] * st.rho;
+        Essb = w[4];
+        bnb += w[5] + x[5];
+        b1b = w[6];
+        b2b = w[7];
+        stb.v1 = x[2] * st.rho;
+        stb.v2 = x[3] * st.rho;
+        Esb = x[4];
+        stb.b1 = x[6];
+        stb.b2 = x[7];
     }
     const T s_out_b = outer ? T(0) : a1b;
     const T s_in_b = (outer || !dbl) ? T(0) : a2b;
-    // E** = E*_a + sig sq_a (vb*_a - vbss) sgn
-    stb.E += Essb;
-    stb.sq += sig * (st.vb - vbss) * sgn * Essb;
-    stb.vb += sig * st.sq * sgn * Essb;
-    vbssb -= sig * st.sq * sgn * Essb;
+    // E** = E* + sig sq* (v*.B* - v**.B**) sgn
+    Esb += Essb;
+    stb.sq = sig * (vbs - vbss) * sgn * Essb;
+    T vbsb = sig * st.sq * sgn * Essb;
+    const T vbssb = -vbsb;
     // vbss = sM bn + v1 b1 + v2 b2
     sMb += bn * vbssb;
     bnb += sM * vbssb;
@@ -370,59 +367,63 @@ __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R,
     b1b += v1 * vbssb;
     v2b += b2 * vbssb;
     b2b += v2 * vbssb;
+    // picked single-star energy: Es = Enum isd, vbs = sM bn + v1* b1* + v2* b2*
+    const T Enumb = Esb * st.isd;
+    stb.isd = Esb * Enum;
+    stb.su = Enumb * S.E;
+    RBar<T> xb;
+    DBar<T> xd;
+    xd.E = Enumb * st.su;
+    xd.pt = -Enumb * S.u;
+    xb.u = -Enumb * S.pt;
+    T ptsb = Enumb * sM;
+    sMb += Enumb * pts;
+    bnb += Enumb * (S.vb - vbs);
+    xd.vb = Enumb * bn;
+    vbsb -= Enumb * bn;
+    sMb += vbsb * bn;
+    bnb += vbsb * sM;
+    stb.v1 += vbsb * st.b1;
+    stb.b1 += vbsb * st.v1;
+    stb.v2 += vbsb * st.b2;
+    stb.b2 += vbsb * st.v2;
     // double-star tangential components
     const T N1b = b1b * iden, N2b = b2b * iden, M1b = v1b * iden, M2b = v2b * iden;
     const T idenb = b1b * N1 + b2b * N2 + v1b * M1 + v2b * M2;
     StarB<T> slb, srb;
-    slb.sq += N1b * sr.b1 + N2b * sr.b2 + M1b * sl.v1 + M2b * sl.v2;
-    srb.sq += N1b * sl.b1 + N2b * sl.b2 + M1b * sr.v1 + M2b * sr.v2;
-    srb.b1 += N1b * sl.sq + M1b * sgn;
-    srb.b2 += N2b * sl.sq + M2b * sgn;
-    slb.b1 += N1b * sr.sq - M1b * sgn;
-    slb.b2 += N2b * sr.sq - M2b * sgn;
     const T sqqb = (N1b * (sr.v1 - sl.v1) + N2b * (sr.v2 - sl.v2)) * sgn;
-    srb.v1 += N1b * sqq * sgn + M1b * sr.sq;
-    slb.v1 += -N1b * sqq * sgn + M1b * sl.sq;
-    srb.v2 += N2b * sqq * sgn + M2b * sr.sq;
-    slb.v2 += -N2b * sqq * sgn + M2b * sl.sq;
-    slb.sq += sqqb * sr.sq;
-    srb.sq += sqqb * sl.sq;
     const T sqsb = -iden * iden * idenb;
-    slb.sq += sqsb;
-    srb.sq += sqsb;
+    slb.sq = N1b * sr.b1 + N2b * sr.b2 + M1b * sl.v1 + M2b * sl.v2 + sqqb * sr.sq + sqsb;
+    srb.sq = N1b * sl.b1 + N2b * sl.b2 + M1b * sr.v1 + M2b * sr.v2 + sqqb * sl.sq + sqsb;
+    srb.b1 = N1b * sl.sq + M1b * sgn;
+    srb.b2 = N2b * sl.sq + M2b * sgn;
+    slb.b1 = N1b * sr.sq - M1b * sgn;
+    slb.b2 = N2b * sr.sq - M2b * sgn;
+    srb.v1 = N1b * sqq * sgn + M1b * sr.sq;
+    slb.v1 = -N1b * sqq * sgn + M1b * sl.sq;
+    srb.v2 = N2b * sqq * sgn + M2b * sr.sq;
+    slb.v2 = -N2b * sqq * sgn + M2b * sl.sq;
     // inner speeds s*L = sM - |bn| isq_L, s*R = sM + |bn| isq_R
-    T abnb = 0;
-    if (left) {
-        sMb += s_in_b;
-        abnb -= s_in_b * sl.isq;
-        slb.isq -= s_in_b * abn;
-    } else {
-        sMb += s_in_b;
-        abnb += s_in_b * sr.isq;
-        srb.isq += s_in_b * abn;
-    }
-    bnb += sgn * abnb;
-    // the side's own star cotangents
-    {
-        const T z = T(0);
-        slb.rho += left ? stb.rho : z; srb.rho += left ? z : stb.rho;
-        slb.v1 += left ? stb.v1 : z; srb.v1 += left ? z : stb.v1;
-        slb.v2 += left ? stb.v2 : z; srb.v2 += left ? z : stb.v2;
-        slb.b1 += left ? stb.b1 : z; srb.b1 += left ? z : stb.b1;
-        slb.b2 += left ? stb.b2 : z; srb.b2 += left ? z : stb.b2;
-        slb.E += left ? stb.E : z; srb.E += left ? z : stb.E;
-        slb.vb += left ? stb.vb : z; srb.vb += left ? z : stb.vb;
-        slb.sq += left ? stb.sq : z; srb.sq += left ? z : stb.sq;
-        slb.isq += left ? stb.isq : z; srb.isq += left ? z : stb.isq;
-    }
-    T sLb = left ? s_out_b : T(0);
-    T sRb = left ? T(0) : s_out_b;
-    T ptsb = 0;
-    star_rev(L, sM, pts, sl, slb, Lb, Ld, sLb, sMb, ptsb, bnb);
-    star_rev(R, sM, pts, sr, srb, Rb, Rd, sRb, sMb, ptsb, bnb);
+    sMb += s_in_b;
+    slb.isq = -wl * s_in_b * abn;
+    srb.isq = wr * s_in_b * abn;
+    bnb += sgn * s_in_b * (wr * sr.isq - wl * sl.isq);
+    // the picked side's own star cotangents
+    slb.rho = wl * stb.rho; srb.rho = wr * stb.rho;
+    slb.v1 += wl * stb.v1; srb.v1 += wr * stb.v1;
+    slb.v2 += wl * stb.v2; srb.v2 += wr * stb.v2;
+    slb.b1 += wl * stb.b1; srb.b1 += wr * stb.b1;
+    slb.b2 += wl * stb.b2; srb.b2 += wr * stb.b2;
+    slb.sq += wl * stb.sq; srb.sq += wr * stb.sq;
+    slb.su = wl * stb.su; srb.su = wr * stb.su;
+    slb.isd = wl * stb.isd; srb.isd = wr * stb.isd;
+    T sLb = wl * s_out_b;
+    T sRb = wr * s_out_b;
+    star_rev(L, sM, sl, slb, Lb, sLb, sMb, bnb);
+    star_rev(R, sM, sr, srb, Rb, sRb, sMb, bnb);
     // pts = npt idm, sM = nsM idm
     const T nptb = ptsb * idm;
-    T idmb = ptsb * npt + sMb * nsM;
+    const T idmb = ptsb * npt + sMb * nsM;
     const T nsMb = sMb * idm;
     T mRb = nptb * (L.pt + mL * du) + nsMb * R.u;
     T mLb = nptb * (-R.pt + mR * du) - nsMb * L.u;
@@ -443,15 +444,20 @@ __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R,
     T cLb = 0, cRb = 0;
     if (selx) { Lb.u += sLb; cLb -= sLb; } else { Rb.u += sLb; cRb -= sLb; }
     if (sely) { Lb.u += sRb; cLb += sRb; } else { Rb.u += sRb; cRb += sRb; }
-    // flux and conserved vector of the side state (F = f + a1 (us - u) + ...)
-    {
-        RBar<T> xb;
-        DBar<T> xd;
-        flux_rev(S, Fb, ub, xb, xd);
-        add_picked(left, xb, xd, Lb, Ld, Rb, Rd);
-    }
-    fast_rev(L, ph, cL, cLb, Lb, Ld);
-    fast_rev(R, ph, cR, cRb, Rb, Rd);
+    // flux, conserved vector and energy of the picked side
+    flux_rev(S, Fb, ub, xb, xd);
+    energy_rev(S, ph, xd.E, xd.vb, xb);
+    Lb.rho += wl * xb.rho; Rb.rho += wr * xb.rho;
+    Lb.u += wl * xb.u; Rb.u += wr * xb.u;
+    Lb.v1 += wl * xb.v1; Rb.v1 += wr * xb.v1;
+    Lb.v2 += wl * xb.v2; Rb.v2 += wr * xb.v2;
+    Lb.p += wl * xb.p; Rb.p += wr * xb.p;
+    Lb.bn += wl * xb.bn; Rb.bn += wr * xb.bn;
+    Lb.b1 += wl * xb.b1; Rb.b1 += wr * xb.b1;
+    Lb.b2 += wl * xb.b2; Rb.b2 += wr * xb.b2;
+    Ld.pt += wl * xd.pt; Rd.pt += wr * xd.pt;
+    fast_rev(L, ph, cL, sdL, cLb, Lb, Ld);
+    fast_rev(R, ph, cR, sdR, cRb, Rb, Rd);
 }
 
 // VJP of face_flux along a compile-time axis D: given gb = dJ/dF (9 comps,
@@ -473,8 +479,8 @@ __device__ __forceinline__ void face_flux_vjp(const T *VL, const T *VR, const Ph
     L.bn = bns; L.b1 = VL[BX + d1]; L.b2 = VL[BX + d2];
     R.rho = VR[RHO]; R.u = VR[VX + D]; R.v1 = VR[VX + d1]; R.v2 = VR[VX + d2]; R.p = VR[PRS];
     R.bn = bns; R.b1 = VR[BX + d1]; R.b2 = VR[BX + d2];
-    rstate_finish(L, ph);
-    rstate_finish(R, ph);
+    rstate_prepare(L);
+    rstate_prepare(R);
     const T fb[8] = {gb[RHO], gb[MX + D], gb[MX + d1], gb[MX + d2], gb[ENG], T(0), gb[BX + d1], gb[BX + d2]};
     const T psisb = ph.glm ? gb[BX + D] : T(0);
     T bnsb = ph.glm ? ph.ch2 * gb[PSI] : T(0);
@@ -484,8 +490,8 @@ __device__ __forceinline__ void face_flux_vjp(const T *VL, const T *VR, const Ph
         hlld_vjp(L, R, ph, fb, Lb, Rb, Ld, Rd, bnsb);
     else
         hll_vjp(L, R, ph, fb, Lb, Rb, Ld, Rd, bnsb);
-    finish_rev(L, ph, Ld, Lb);
-    finish_rev(R, ph, Rd, Rb);
+    prepare_rev(L, Ld, Lb);
+    prepare_rev(R, Rd, Rb);
     bnsb += Lb.bn + Rb.bn;
     VLb[RHO] = Lb.rho; VLb[VX + D] = Lb.u; VLb[VX + d1] = Lb.v1; VLb[VX + d2] = Lb.v2;
     VLb[PRS] = Lb.p; VLb[BX + d1] = Lb.b1; VLb[BX + d2] = Lb.b2;
@@ -500,8 +506,8 @@ __device__ __forceinline__ void face_flux_vjp(const T *VL, const T *VR, const Ph
 
 // limited slope with its derivative coefficients (dp, dq) w.r.t. the
 // backward and forward differences a and b
-template <typename T>
-__device__ __forceinline__ T slope_d(T a, T b, int limiter, T &dp, T &dq)
+template <int LIM, typename T>
+__device__ __forceinline__ T slope_d(T a, T b, T &dp, T &dq)
 {
     const T aa = Num<T>::abs(a), ab = Num<T>::abs(b);
     const bool pos = a * b > T(0);
@@ -509,7 +515,7 @@ __device__ __forceinline__ T slope_d(T a, T b, int limiter, T &dp, T &dq)
     T m = left ? a : b;
     T cp = left ? T(1) : T(0), cq = left ? T(0) : T(1);
     T c0 = T(0.5);
-    if (limiter == LIM_MC) {
+    if (LIM == LIM_MC) {
         const T two = T(2) * m, cen = T(0.5) * (a + b);
         const bool tw = Num<T>::abs(two) <= Num<T>::abs(cen);
         m = tw ? two : cen;
@@ -577,46 +583,54 @@ template <typename T> struct AdjStageArgs {
 // cell item of one component: returns E_c (with the outflow substitutions
 // for the boundary cells), sets A_c and B_c (substituted for the ghosts)
 struct CellFlags {
+    bool outflow;  // the axis is outflow (uniform over the grid)
     bool ghost_lo, first, ghost_hi, last;
 };
 __device__ __forceinline__ CellFlags cell_flags(int c, int n, int per)
 {
     CellFlags f;
-    f.ghost_lo = !per && c == -1;
-    f.first = !per && c == 0;
-    f.ghost_hi = !per && c == n;
-    f.last = !per && c == n - 1;
+    f.outflow = !per;
+    f.ghost_lo = c == -1;
+    f.first = c == 0;
+    f.ghost_hi = c == n;
+    f.last = c == n - 1;
     return f;
 }
 
 template <typename T>
-__device__ __forceinline__ T cell_item(T vl, T vr, T wm, T w0, T wp, int limiter, CellFlags fl, T &A,
-                                       T &B)
+__device__ __forceinline__ T cell_item_d(T vl, T vr, T dp, T dq, CellFlags fl, T &A, T &B)
 {
     const T sb = T(0.5) * (vl - vr);
-    T dp, dq;
-    slope_d(w0 - wm, wp - w0, limiter, dp, dq);
     A = sb * dp;
     B = sb * dq;
     T E = vl + vr + A - B;
-    E = fl.first ? E - A : E;
-    E = fl.last ? E + B : E;
-    B = fl.ghost_lo ? vl : B;
-    A = fl.ghost_hi ? -vr : A;
+    if (fl.outflow) {
+        E = fl.first ? E - A : E;
+        E = fl.last ? E + B : E;
+        B = fl.ghost_lo ? vl : B;
+        A = fl.ghost_hi ? -vr : A;
+    }
     return E;
 }
 
-// extended index -> cell index along an axis for the cotangent v (-1: zero)
+template <int LIM, typename T>
+__device__ __forceinline__ T cell_item(T vl, T vr, T wm, T w0, T wp, CellFlags fl, T &A, T &B)
+{
+    T dp, dq;
+    slope_d<LIM>(w0 - wm, wp - w0, dp, dq);
+    return cell_item_d(vl, vr, dp, dq, fl, A, B);
+}
+
+
+// extended index -> cell index along an axis for the cotangent v (-1: zero
+// outside an outflow axis); the periodic wrap is remap_index's
 __device__ __forceinline__ int v_index(int m, int n, int per)
 {
-    if (per) {
-        m %= n;
-        return m < 0 ? m + n : m;
-    }
+    if (per) return remap_index(m, n, 1);
     return (m < 0 || m >= n) ? -1 : m;
 }
 
-template <typename T, int SOLVER, int NDIM, int PASS, int TY>
+template <typename T, int SOLVER, int LIM, int NDIM, int PASS, int TY>
 __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T> a)
 {
     constexpr int NT = TX * TY;
@@ -720,8 +734,8 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
         for (int q = 0; q < NQ; ++q) {
             const T *pq = base + q * PLANE;
             const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride];
-            VL[q] = w1 + T(0.5) * limited_slope(w1 - w0, w2 - w1, a.ph.limiter);
-            VR[q] = w2 - T(0.5) * limited_slope(w2 - w1, w3 - w2, a.ph.limiter);
+            VL[q] = w1 + T(0.5) * limited_slope<LIM>(w1 - w0, w2 - w1);
+            VR[q] = w2 - T(0.5) * limited_slope<LIM>(w2 - w1, w3 - w2);
         }
         face_flux_vjp<T, SOLVER, D>(VL, VR, a.ph, gb, VLb, VRb);
     };
@@ -732,8 +746,8 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
         for (int q = 0; q < NQ; ++q) {
             const T *w = wc + q * PLANE;
             T A, B;
-            const T e = cell_item(vl[q * fstride], vr[q * fstride], w[-wstride], w[0], w[wstride],
-                                  a.ph.limiter, fl, A, B);
+            const T e = cell_item<LIM>(vl[q * fstride], vr[q * fstride], w[-wstride], w[0], w[wstride],
+                                       fl, A, B);
             vl[q * fstride] = A;
             vr[q * fstride] = B;
             if (E) E[q] += e;
@@ -806,7 +820,7 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
             __syncthreads();
         }
         // (b) z-face kk+2 and the z cell item of kk+1 (planes kk .. kk+3
-        // reloaded, they are cache resident); R starts as Wb_z of plane kk
+        // re-read, they are cache resident); R starts as Wb_z of plane kk
         T R[NQ];
         if (NDIM == 3) {
             T gb[NQ], VL[NQ], VR[NQ], VLb[NQ], VRb[NQ];
@@ -818,8 +832,8 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
                 prim_at(zoff(kk + 3) + own, w3);
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    VL[q] = w1[q] + T(0.5) * limited_slope(w1[q] - w0[q], w2[q] - w1[q], a.ph.limiter);
-                    VR[q] = w2[q] - T(0.5) * limited_slope(w2[q] - w1[q], w3[q] - w2[q], a.ph.limiter);
+                    VL[q] = w1[q] + T(0.5) * limited_slope<LIM>(w1[q] - w0[q], w2[q] - w1[q]);
+                    VR[q] = w2[q] - T(0.5) * limited_slope<LIM>(w2[q] - w1[q], w3[q] - w2[q]);
                 }
             }
             const int za = v_index(kk + 1, a.nz, a.per[2]), zb = v_index(kk + 2, a.nz, a.per[2]);
@@ -833,7 +847,7 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 T A, B;
-                const T E = cell_item(VLb[q], VRz[q], w0[q], w1[q], w2[q], a.ph.limiter, fl, A, B);
+                const T E = cell_item<LIM>(VLb[q], VRz[q], w0[q], w1[q], w2[q], fl, A, B);
                 R[q] = Xz[q] - A;
                 Xz[q] = E + Bz[q];
                 Bz[q] = B;
@@ -853,6 +867,17 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
                 const int go = (ty + 1) * TX + tx;  // slot of face j (own cell's lower y face)
                 lds_cell(&P[own_slot], PX, &FY[go + TX], &FY[NQ * NFY + go], NFY,
                          cell_flags(j, a.ny, a.per[1]), R);
+            }
+        }
+        // the lambda values of the own cell that the combine needs are loaded
+        // here, so that their latency overlaps the halo items and the barrier
+        double mu[NQ], l1[NQ];
+        if (active) {
+            const long long c = zk + own;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                mu[q] = a.lamp[q * a.ncell + c] * (q == PSI ? a.damp : 1.0);
+                l1[q] = PASS == 1 ? a.lam1[q * a.ncell + c] : 0.0;
             }
         }
         for (int hc = TY - 1 - wave; hc < NCCH; hc += TY) {
@@ -876,7 +901,8 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
             }
         }
         __syncthreads();
-        // (f) neighbours' A and B, FP64 sum over axes, transpose, combine
+        // (f) neighbours' A and B, the primitive -> conserved transpose at
+        // the cell's primitives (in LDS) and the lambda combination, in FP64
         if (active) {
             double wb[NQ];
             {
@@ -891,12 +917,9 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
                     wb[q] = r;
                 }
             }
-            const long long c = zk + own;
-            double u[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) u[q] = (double)a.U[q * a.ncell + c];
-            const double ir = 1.0 / u[RHO];
-            const double v[3] = {u[MX] * ir, u[MY] * ir, u[MZ] * ir};
+            const T *w = &P[own_slot];
+            const double ir = 1.0 / (double)w[RHO * PLANE];
+            const double v[3] = {(double)w[VX * PLANE], (double)w[VY * PLANE], (double)w[VZ * PLANE]};
             const double vsq = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
             double r[NQ];
             r[RHO] = wb[RHO] - (v[0] * wb[VX] + v[1] * wb[VY] + v[2] * wb[VZ]) * ir +
@@ -904,18 +927,18 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 r[MX + k] = wb[VX + k] * ir - a.gm1 * v[k] * wb[PRS];
-                r[BX + k] = wb[BX + k] - a.gm1 * u[BX + k] * wb[PRS];
+                r[BX + k] = wb[BX + k] - a.gm1 * (double)w[(BX + k) * PLANE] * wb[PRS];
             }
             r[ENG] = a.gm1 * wb[PRS];
             r[PSI] = wb[PSI];
+            const long long c = zk + own;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const double mu = a.lamp[q * a.ncell + c] * (q == PSI ? a.damp : 1.0);
                 double o;
                 if (PASS == 2)
-                    o = 0.5 * mu + 0.5 * a.dt * r[q];
+                    o = 0.5 * mu[q] + 0.5 * a.dt * r[q];
                 else
-                    o = 0.5 * mu + a.lam1[q * a.ncell + c] + a.dt * r[q];
+                    o = 0.5 * mu[q] + l1[q] + a.dt * r[q];
                 a.out[q * a.ncell + c] = o;
             }
         }

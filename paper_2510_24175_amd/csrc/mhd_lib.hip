@@ -99,11 +99,10 @@ template <typename T> Phys<T> make_phys(const mhd_ctx *ctx, double ch)
     p.ch = (T)(p.glm ? ch : 0.0);
     p.ch2 = (T)(p.glm ? ch * ch : 0.0);
     p.half_ich = (T)(p.glm ? 0.5 / ch : 0.0);
-    p.limiter = ctx->cfg.limiter;
     return p;
 }
 
-template <typename T, int SOLVER, int NDIM>
+template <typename T, int SOLVER, int LIM, int NDIM>
 mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, double ch, double damp)
 {
     constexpr int TY = tile_rows<T, NDIM>();
@@ -120,7 +119,6 @@ mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, do
     for (int d = 0; d < 3; ++d) {
         a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
         a.idx[d] = (T)(1.0 / ctx->dx[d]);
-        a.idx_f[d] = (float)(1.0 / ctx->dx[d]);
         a.idx_d[d] = 1.0 / ctx->dx[d];
     }
     a.kz = L.kz;
@@ -139,14 +137,14 @@ mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, do
     a.uin = un;
     a.un = un;
     a.uout = u1;
-    hipLaunchKernelGGL((stage_kernel<T, SOLVER, NDIM, 1, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+    hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 1, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
                        ctx->stream, a);
     HIP_TRY(ctx, hipGetLastError());
     if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
     a.uin = u1;
     a.un = un;
     a.uout = unext;
-    hipLaunchKernelGGL((stage_kernel<T, SOLVER, NDIM, 2, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+    hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 2, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
                        ctx->stream, a);
     HIP_TRY(ctx, hipGetLastError());
     if (ev) HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
@@ -157,16 +155,16 @@ mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, do
     return MHD_OK;
 }
 
-template <typename T, int SOLVER>
+template <typename T, int SOLVER, int LIM>
 mhd_status launch_step_nd(mhd_ctx *ctx, const void *un, void *unext, void *u1, double dt, double ch,
                           double damp)
 {
     const T *a = (const T *)un;
     T *b = (T *)unext, *c = (T *)u1;
     switch (ctx->cfg.ndim) {
-    case 1: return launch_step<T, SOLVER, 1>(ctx, a, b, c, dt, ch, damp);
-    case 2: return launch_step<T, SOLVER, 2>(ctx, a, b, c, dt, ch, damp);
-    default: return launch_step<T, SOLVER, 3>(ctx, a, b, c, dt, ch, damp);
+    case 1: return launch_step<T, SOLVER, LIM, 1>(ctx, a, b, c, dt, ch, damp);
+    case 2: return launch_step<T, SOLVER, LIM, 2>(ctx, a, b, c, dt, ch, damp);
+    default: return launch_step<T, SOLVER, LIM, 3>(ctx, a, b, c, dt, ch, damp);
     }
 }
 
@@ -178,7 +176,7 @@ template <typename T, int NDIM> constexpr int adj_tile_rows()
     return NDIM == 1 ? 1 : (sizeof(T) == 4 ? 8 : 4);
 }
 
-template <typename T, int SOLVER, int NDIM, int PASS>
+template <typename T, int SOLVER, int LIM, int NDIM, int PASS>
 mhd_status launch_adj_stage(mhd_ctx *ctx, const T *U, const double *lamp, const double *lam1,
                             double *out, double dt, double ch, double damp)
 {
@@ -208,13 +206,13 @@ mhd_status launch_adj_stage(mhd_ctx *ctx, const T *U, const double *lamp, const 
     a.damp = damp;
     a.gm1 = ctx->cfg.gamma - 1.0;
     a.ph = make_phys<T>(ctx, ch);
-    hipLaunchKernelGGL((adj_stage_kernel<T, SOLVER, NDIM, PASS, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+    hipLaunchKernelGGL((adj_stage_kernel<T, SOLVER, LIM, NDIM, PASS, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
                        ctx->stream, a);
     HIP_TRY(ctx, hipGetLastError());
     return MHD_OK;
 }
 
-template <typename T, int SOLVER, int NDIM>
+template <typename T, int SOLVER, int LIM, int NDIM>
 mhd_status launch_adjoint(mhd_ctx *ctx, const T *un, const T *u1, const double *lamp, double *lamn,
                           double dt, double ch, double damp)
 {
@@ -233,8 +231,7 @@ mhd_status launch_adjoint(mhd_ctx *ctx, const T *un, const T *u1, const double *
         for (int d = 0; d < 3; ++d) {
             a.per[d] = ctx->cfg.bc[d][0] == MHD_PERIODIC;
             a.idx[d] = (T)(1.0 / ctx->dx[d]);
-            a.idx_f[d] = (float)(1.0 / ctx->dx[d]);
-            a.idx_d[d] = 1.0 / ctx->dx[d];
+                a.idx_d[d] = 1.0 / ctx->dx[d];
         }
         a.kz = L.kz;
         a.tiles_x = L.tiles_x;
@@ -248,30 +245,49 @@ mhd_status launch_adjoint(mhd_ctx *ctx, const T *un, const T *u1, const double *
         a.uin = un;
         a.un = un;
         a.uout = (T *)ctx->u1_scratch;
-        hipLaunchKernelGGL((stage_kernel<T, SOLVER, NDIM, 1, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 1, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
                            ctx->stream, a);
         HIP_TRY(ctx, hipGetLastError());
         u1 = (const T *)ctx->u1_scratch;
     }
     // stage-2 pass: lam1 = mu/2 + (dt/2) J_L(U1)^T mu, mu = D lam'
-    mhd_status st = launch_adj_stage<T, SOLVER, NDIM, 2>(ctx, u1, lamp, nullptr, ctx->lam1, dt, ch, damp);
+    mhd_status st = launch_adj_stage<T, SOLVER, LIM, NDIM, 2>(ctx, u1, lamp, nullptr, ctx->lam1, dt, ch, damp);
     if (st != MHD_OK) return st;
     // stage-1 pass: lamn = mu/2 + lam1 + dt J_L(Un)^T lam1
-    st = launch_adj_stage<T, SOLVER, NDIM, 1>(ctx, un, lamp, ctx->lam1, lamn, dt, ch, damp);
+    st = launch_adj_stage<T, SOLVER, LIM, NDIM, 1>(ctx, un, lamp, ctx->lam1, lamn, dt, ch, damp);
     if (st != MHD_OK) return st;
     return MHD_OK;
 }
 
-template <typename T, int SOLVER>
+template <typename T, int SOLVER, int LIM>
 mhd_status launch_adjoint_nd(mhd_ctx *ctx, const void *un, const void *u1, const double *lamp,
                              double *lamn, double dt, double ch, double damp)
 {
     const T *a = (const T *)un, *b = (const T *)u1;
     switch (ctx->cfg.ndim) {
-    case 1: return launch_adjoint<T, SOLVER, 1>(ctx, a, b, lamp, lamn, dt, ch, damp);
-    case 2: return launch_adjoint<T, SOLVER, 2>(ctx, a, b, lamp, lamn, dt, ch, damp);
-    default: return launch_adjoint<T, SOLVER, 3>(ctx, a, b, lamp, lamn, dt, ch, damp);
+    case 1: return launch_adjoint<T, SOLVER, LIM, 1>(ctx, a, b, lamp, lamn, dt, ch, damp);
+    case 2: return launch_adjoint<T, SOLVER, LIM, 2>(ctx, a, b, lamp, lamn, dt, ch, damp);
+    default: return launch_adjoint<T, SOLVER, LIM, 3>(ctx, a, b, lamp, lamn, dt, ch, damp);
     }
+}
+
+// Compile-time scheme: state type, Riemann solver, limiter.
+template <typename T_, int SOLVER_, int LIM_> struct Scheme {
+    using T = T_;
+    static constexpr int SOLVER = SOLVER_;
+    static constexpr int LIM = LIM_;
+};
+
+template <typename Fn> mhd_status with_scheme(const mhd_ctx *ctx, Fn &&fn)
+{
+    const bool mc = ctx->cfg.limiter == MHD_MC;
+    const bool hlld = ctx->cfg.riemann == MHD_HLLD;
+    if (ctx->cfg.dtype == MHD_F32) {
+        if (hlld) return mc ? fn(Scheme<float, SOLVER_HLLD, LIM_MC>{}) : fn(Scheme<float, SOLVER_HLLD, LIM_MINMOD>{});
+        return mc ? fn(Scheme<float, SOLVER_HLL, LIM_MC>{}) : fn(Scheme<float, SOLVER_HLL, LIM_MINMOD>{});
+    }
+    if (hlld) return mc ? fn(Scheme<double, SOLVER_HLLD, LIM_MC>{}) : fn(Scheme<double, SOLVER_HLLD, LIM_MINMOD>{});
+    return mc ? fn(Scheme<double, SOLVER_HLL, LIM_MC>{}) : fn(Scheme<double, SOLVER_HLL, LIM_MINMOD>{});
 }
 
 template <typename T>
@@ -547,14 +563,10 @@ mhd_status mhd_step(mhd_ctx *ctx, const void *Un, void *U_next, void *U1_out, do
     if (ctx->cfg.glm && !finite_pos(c_h)) return fail(ctx, MHD_ERR_ARG, "c_h must be finite and > 0");
     if (!(damp > 0.0 && damp <= 1.0)) return fail(ctx, MHD_ERR_ARG, "damp must be in (0, 1]");
     void *u1 = U1_out ? U1_out : ctx->u1_scratch;
-    mhd_status st;
-    const bool f32 = ctx->cfg.dtype == MHD_F32;
-    if (ctx->cfg.riemann == MHD_HLLD)
-        st = f32 ? launch_step_nd<float, SOLVER_HLLD>(ctx, Un, U_next, u1, dt, c_h, damp)
-                 : launch_step_nd<double, SOLVER_HLLD>(ctx, Un, U_next, u1, dt, c_h, damp);
-    else
-        st = f32 ? launch_step_nd<float, SOLVER_HLL>(ctx, Un, U_next, u1, dt, c_h, damp)
-                 : launch_step_nd<double, SOLVER_HLL>(ctx, Un, U_next, u1, dt, c_h, damp);
+    const mhd_status st = with_scheme(ctx, [&](auto sch) {
+        using S = decltype(sch);
+        return launch_step_nd<typename S::T, S::SOLVER, S::LIM>(ctx, Un, U_next, u1, dt, c_h, damp);
+    });
     if (st == MHD_OK) ctx->have_step = true;
     return st;
 }
@@ -585,12 +597,10 @@ mhd_status mhd_step_adjoint(mhd_ctx *ctx, const void *Un, const void *U1, const 
         return fail(ctx, MHD_ERR_ARG, "context was created without MHD_FLAG_ADJOINT");
     if ((const void *)lam_n == Un || (const void *)lam_n == U1)
         return fail(ctx, MHD_ERR_ARG, "lam_n must not alias a state buffer");
-    const bool f32 = ctx->cfg.dtype == MHD_F32;
-    if (ctx->cfg.riemann == MHD_HLLD)
-        return f32 ? launch_adjoint_nd<float, SOLVER_HLLD>(ctx, Un, U1, lam_next, lam_n, dt, c_h, damp)
-                   : launch_adjoint_nd<double, SOLVER_HLLD>(ctx, Un, U1, lam_next, lam_n, dt, c_h, damp);
-    return f32 ? launch_adjoint_nd<float, SOLVER_HLL>(ctx, Un, U1, lam_next, lam_n, dt, c_h, damp)
-               : launch_adjoint_nd<double, SOLVER_HLL>(ctx, Un, U1, lam_next, lam_n, dt, c_h, damp);
+    return with_scheme(ctx, [&](auto sch) {
+        using S = decltype(sch);
+        return launch_adjoint_nd<typename S::T, S::SOLVER, S::LIM>(ctx, Un, U1, lam_next, lam_n, dt, c_h, damp);
+    });
 }
 
 } // extern "C"

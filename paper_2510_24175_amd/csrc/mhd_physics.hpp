@@ -57,7 +57,6 @@ template <typename T> struct Phys {
     T ch2;       // c_h^2
     T half_ich;  // 1 / (2 c_h), 0 when GLM is off
     int glm;     // GLM cleaning on
-    int limiter; // LIM_MINMOD or LIM_MC
 };
 
 // Conserved -> primitive.  Returns false for rho <= 0, p <= 0 or a
@@ -87,10 +86,11 @@ __device__ __forceinline__ bool cons_to_prim(const T *u, const Phys<T> &ph, T *v
 
 // Limited slope from the backward difference a and the forward difference b:
 // minmod(a, b), or MC = minmod(2a, 2b, (a+b)/2).
-template <typename T> __device__ __forceinline__ T limited_slope(T a, T b, int limiter)
+// The limiter is a compile-time parameter of the kernels.
+template <int LIM, typename T> __device__ __forceinline__ T limited_slope(T a, T b)
 {
     T m = Num<T>::min(Num<T>::abs(a), Num<T>::abs(b));
-    if (limiter == LIM_MC) m = Num<T>::min(T(2) * m, T(0.5) * Num<T>::abs(a + b));
+    if (LIM == LIM_MC) m = Num<T>::min(T(2) * m, T(0.5) * Num<T>::abs(a + b));
     return (a * b > T(0)) ? Num<T>::copysign(m, a) : T(0);
 }
 
@@ -348,14 +348,18 @@ __device__ __forceinline__ void face_flux(const T *VL, const T *VR, int d, const
     F[PSI] = ph.glm ? ph.ch2 * bns : T(0);
 }
 
-// Boundary index map of a ghost or interior coordinate m on an axis of n
-// cells: periodic wrap or zero-gradient clamp.  Valid for any m (values
-// beyond the two ghost layers are only ever used as padding).
+// Boundary index map of a ghost or interior coordinate m on an axis of n >= 2
+// cells: periodic wrap or zero-gradient clamp.  The wrap folds at most twice
+// (no integer division), so it is exact for m in [-2n, 3n), which holds every
+// position a stencil of an interior cell reaches (m in [-3, n + 3)); other
+// coordinates, used only as padding, are clamped into the axis.
 __device__ __forceinline__ int remap_index(int m, int n, int periodic)
 {
     if (periodic) {
-        m %= n;
-        return m < 0 ? m + n : m;
+        m = m < 0 ? m + n : m;
+        m = m < 0 ? m + n : m;
+        m = m >= n ? m - n : m;
+        m = m >= n ? m - n : m;
     }
     return m < 0 ? 0 : (m >= n ? n - 1 : m);
 }

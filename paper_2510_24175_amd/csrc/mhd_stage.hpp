@@ -48,7 +48,6 @@ template <typename T> struct StageArgs {
     int nblocks;
     T dt;
     T idx[3];       // 1/dx per axis
-    float idx_f[3]; // 1/dx per axis (FP32 speed estimates)
     T damp;
     double gamma_d; // FP64 copies for the reductions
     double idx_d[3];
@@ -87,35 +86,6 @@ __device__ __forceinline__ bool cell_speeds(const T *u, double gamma, const doub
     return ok;
 }
 
-// FP32 estimate of the same speeds (hardware reciprocal and square roots),
-// used to decide which cells need the exact FP64 evaluation.  Returns false
-// for a non-physical or non-finite state.
-template <int NDIM>
-__device__ __forceinline__ bool cell_speeds_estimate(const float *u, float gamma, float gm1,
-                                                     const float *idx, float &s, float &c)
-{
-    const float ir = Num<float>::rcp(u[RHO]);
-    const float bsq = u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ];
-    const float kin = 0.5f * (u[MX] * u[MX] + u[MY] * u[MY] + u[MZ] * u[MZ]) * ir;
-    const float p = gm1 * (u[ENG] - kin - 0.5f * bsq);
-    s = 0.f;
-    c = 0.f;
-#pragma unroll
-    for (int d = 0; d < NDIM; ++d) {
-        const float lam = Num<float>::abs(u[MX + d] * ir) + fast_speed(u[RHO], p, bsq, u[BX + d] * u[BX + d], gamma, ir);
-        s = Num<float>::max(s, lam * idx[d]);
-        c = Num<float>::max(c, lam);
-    }
-    return (u[RHO] > 0.f) & (p > 0.f) & (s < 3.0e38f);
-}
-
-__device__ __forceinline__ float wave_max_f(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = Num<float>::max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 template <typename T>
 __device__ __forceinline__ void load_cell(const T *__restrict__ U, long long ncell, long long c, T *u)
 {
@@ -141,7 +111,7 @@ __device__ __forceinline__ double wave_max(double v)
 // with 4-wave workgroups three of them share a compute unit.
 template <typename T> constexpr int stage_min_waves() { return sizeof(T) == 4 ? 3 : 1; }
 
-template <typename T, int SOLVER, int NDIM, int STAGE, int TY>
+template <typename T, int SOLVER, int LIM, int NDIM, int STAGE, int TY>
 __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(const StageArgs<T> a)
 {
     constexpr int NT = TX * TY;
@@ -219,7 +189,7 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
     };
     auto slope9 = [&](const T *vm, const T *v0, const T *vp, T *s) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) s[q] = limited_slope(v0[q] - vm[q], vp[q] - v0[q], a.ph.limiter);
+        for (int q = 0; q < NQ; ++q) s[q] = limited_slope<LIM>(v0[q] - vm[q], vp[q] - v0[q]);
     };
 
     // One face of the plane from the LDS stencil w0..w3 (stride apart):
@@ -232,8 +202,8 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
         for (int q = 0; q < NQ; ++q) {
             const T *pq = base + q * PLANE;
             const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride];
-            const T s1 = limited_slope(w1 - w0, w2 - w1, a.ph.limiter);
-            const T s2 = limited_slope(w2 - w1, w3 - w2, a.ph.limiter);
+            const T s1 = limited_slope<LIM>(w1 - w0, w2 - w1);
+            const T s2 = limited_slope<LIM>(w2 - w1, w3 - w2);
             VL[q] = w1 + T(0.5) * s1;
             VR[q] = w2 - T(0.5) * s2;
         }
@@ -266,7 +236,6 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
     }
 
     double smax = 0.0, cmax = 0.0;
-    float ws32 = 0.f, wc32 = 0.f;  // running FP32 maxima of this wave (FP32 states)
     double sum[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) sum[q] = 0.0;
@@ -327,7 +296,6 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
         }
         __syncthreads();
         // (d) divergence and stage combine
-        float s32 = 0.f, c32 = 0.f;
         if (active) {
             const long long c = zk + own;
             T L[NQ];
@@ -357,26 +325,11 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
             if (STAGE == 2) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) sum[q] += (double)out[q];
-                if (sizeof(T) == 8) {
-                    ok &= cell_speeds<T, NDIM>(out, a.gamma_d, a.idx_d, smax, cmax);
-                } else {
-                    // Exact FP64 speeds only where they can change this wave's
-                    // maxima: a cell whose FP32 estimate is below 0.99 of the
-                    // wave's running FP32 maximum over earlier planes cannot
-                    // hold the wave's FP64 maximum (the estimate is within
-                    // ~1e-6 of the FP64 value), so it is skipped.
-                    const float *o32 = reinterpret_cast<const float *>(out);
-                    const bool ok32 = cell_speeds_estimate<NDIM>(o32, a.ph.gamma, a.ph.gm1, a.idx_f, s32, c32);
-                    const bool cand = (s32 >= 0.99f * ws32) | (c32 >= 0.99f * wc32) | !ok32;
-                    if (__any(cand)) {
-                        if (cand) ok &= cell_speeds<T, NDIM>(out, a.gamma_d, a.idx_d, smax, cmax);
-                    }
-                }
+                // FP64 signal speeds of every updated cell (a filter on an FP32
+                // estimate measured slower: some lane of a wave nearly always
+                // needs the exact value)
+                ok &= cell_speeds<T, NDIM>(out, a.gamma_d, a.idx_d, smax, cmax);
             }
-        }
-        if (STAGE == 2 && sizeof(T) == 4) {
-            ws32 = Num<float>::max(ws32, wave_max_f(s32));
-            wc32 = Num<float>::max(wc32, wave_max_f(c32));
         }
         if (NDIM == 3) {
 #pragma unroll

@@ -10,8 +10,8 @@ benchmark uses.
 * 128^3 turbulence, FP64: full-grid comparison after 10 steps (100 steps
   with MHD_FULL_CHECKS=1).
 * 1024^2 Orszag-Tang: 10 FP32 steps against the oracle on the full grid;
-  the whole run to t = 0.5 in FP64 and FP32 checked for conservation and
-  for the 180-degree rotation symmetry of the setup.
+  the whole run to t = 0.5 (Courant number 0.15) in FP64 and FP32 checked
+  for conservation and for the 180-degree rotation symmetry of the setup.
 """
 import os
 
@@ -124,9 +124,17 @@ def test_orszag_tang_1024():
     assert err.max() <= 1e-5
     o_sums0 = o.sums(o.prim_to_cons(V))
     scale = np.array([np.abs(Uo[q]).sum() for q in range(9)]) * o.cell_volume
-    for dtype, sym_tol, cons_tol in [("f64", 1e-9, 1e-12), ("f32", 1e-3, 1e-6)]:
-        _say(f"[gpu-fullsize] Orszag-Tang 1024^2 {dtype} to t = 0.5")
-        ctx = Context(s, dtype)
+    # The run to t = 0.5 uses Courant number 0.15: without floors this scheme
+    # (PLM minmod + HLLD + GLM, SSP-RK2) loses pressure positivity on this
+    # setup at 1024^2 for 0.2 - 0.3 in FP64 (the FP64 oracle at 0.3 fails at
+    # t = 0.398, as the GPU path does).  The point symmetry holds up to
+    # rounding differences that the shock interactions amplify: the FP64
+    # oracle's own asymmetry on this setup at 512^2 (4372 steps) is 4.3e-6,
+    # and the GPU FP64 state there differs from the oracle's by 6e-6 (rel L1).
+    s_long = dict(s, cfl=0.15)
+    for dtype, sym_tol, cons_tol in [("f64", 5e-5, 1e-12), ("f32", 5e-5, 1e-6)]:
+        _say(f"[gpu-fullsize] Orszag-Tang 1024^2 {dtype} to t = 0.5 (Courant 0.15)")
+        ctx = Context(s_long, dtype)
         U0 = ctx.prim_to_cons(torch.from_numpy(V).cuda())
         U, t, hist = advance(ctx, U0, t_end=s["t_end"])
         _, _, sums = ctx.step_info()
