@@ -876,7 +876,10 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
             const long long c = zk + own;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                mu[q] = a.lamp[q * a.ncell + c] * (q == PSI ? a.damp : 1.0);
+                // pass 1 reads lam' only here (streaming); pass 2 read it for the faces
+                const double lp = PASS == 1 ? __builtin_nontemporal_load(&a.lamp[q * a.ncell + c])
+                                            : a.lamp[q * a.ncell + c];
+                mu[q] = lp * (q == PSI ? a.damp : 1.0);
                 l1[q] = PASS == 1 ? a.lam1[q * a.ncell + c] : 0.0;
             }
         }
@@ -939,7 +942,7 @@ __global__ void __launch_bounds__(TX *TY) adj_stage_kernel(const AdjStageArgs<T>
                     o = 0.5 * mu[q] + 0.5 * a.dt * r[q];
                 else
                     o = 0.5 * mu[q] + l1[q] + a.dt * r[q];
-                a.out[q * a.ncell + c] = o;
+                __builtin_nontemporal_store(o, &a.out[q * a.ncell + c]);  // written once
             }
         }
     }

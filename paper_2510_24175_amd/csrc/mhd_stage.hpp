@@ -321,7 +321,8 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
                 out[PSI] *= a.damp;
             }
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) a.uout[q * a.ncell + c] = out[q];
+            for (int q = 0; q < NQ; ++q)
+                __builtin_nontemporal_store(out[q], &a.uout[q * a.ncell + c]);  // not read again here
             if (STAGE == 2) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) sum[q] += (double)out[q];

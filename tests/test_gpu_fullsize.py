@@ -131,8 +131,11 @@ def test_orszag_tang_1024():
     # rounding differences that the shock interactions amplify: the FP64
     # oracle's own asymmetry on this setup at 512^2 (4372 steps) is 4.3e-6,
     # and the GPU FP64 state there differs from the oracle's by 6e-6 (rel L1).
+    # Conservation: FP64 to rounding (3e-16 measured); the FP32 state is
+    # rounded at every cell update, and over the 8795 steps the FP64 sums of
+    # the FP32 states drift by 2.3e-6 of sum |q| (measured), so 1e-5.
     s_long = dict(s, cfl=0.15)
-    for dtype, sym_tol, cons_tol in [("f64", 5e-5, 1e-12), ("f32", 5e-5, 1e-6)]:
+    for dtype, sym_tol, cons_tol in [("f64", 5e-5, 1e-12), ("f32", 5e-5, 1e-5)]:
         _say(f"[gpu-fullsize] Orszag-Tang 1024^2 {dtype} to t = 0.5 (Courant 0.15)")
         ctx = Context(s_long, dtype)
         U0 = ctx.prim_to_cons(torch.from_numpy(V).cuda())
