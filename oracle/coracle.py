@@ -8,7 +8,7 @@ FP64) and holds the oracle's own time loop:
   ``|v_d| + c_f,d``), ``dt`` clipped so that ``t`` does not pass ``t_end``,
   ``damp = exp(-alpha c_h dt / dh_min)`` (Dedner et al. 2002 mixed GLM,
   parabolic part applied as an exact decay once per step), then one SSP-RK2
-  step (Shu & Osher 1988).
+  or SSP-RK3 step (Shu & Osher 1988).
 
 Arrays are numpy float64, structure-of-arrays ``[9][nz][ny][nx]``.
 """
@@ -21,7 +21,7 @@ import numpy as np
 from . import build as _build
 
 _RIEMANN = {"hll": 0, "hlld": 1}
-_LIMITER = {"minmod": 0, "mc": 1}
+_LIMITER = {"minmod": 0, "mc": 1, "wenoz": 2}
 _BC = {"periodic": 0, "outflow": 1}
 
 
@@ -38,6 +38,8 @@ class _Cfg(ctypes.Structure):
         ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double),
         ("glm_alpha", ctypes.c_double),
+        ("time_order", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -67,6 +69,8 @@ def lib():
         L.orc_fast_speed.restype = ctypes.c_double
         L.orc_limited_slope.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
         L.orc_limited_slope.restype = ctypes.c_double
+        L.orc_wenoz.argtypes = [dp]
+        L.orc_wenoz.restype = ctypes.c_double
         L.orc_glm_interface.argtypes = [ctypes.c_double] * 5 + [dp]
         L.orc_glm_interface.restype = None
         L.orc_hlld_fan.argtypes = [dp, dp, ctypes.c_double, dp]
@@ -116,6 +120,7 @@ class Oracle:
         c.gamma = float(setup["gamma"])
         c.cfl = float(setup["cfl"])
         c.glm_alpha = float(setup.get("glm_alpha", 0.1))
+        c.time_order = int(setup.get("time_order", 2))
         self.cfg = c
         self.shape = (9, int(setup["n"][2]), int(setup["n"][1]), int(setup["n"][0]))
         self.ndim = c.ndim
@@ -214,6 +219,12 @@ def fast_speed(V9, gamma, d):
 
 def limited_slope(limiter, a, b):
     return lib().orc_limited_slope(_LIMITER[limiter], float(a), float(b))
+
+
+def wenoz(v5):
+    """WENO-Z value at the right face of the middle of five cell values."""
+    v = _f64(np.asarray(v5, dtype=np.float64).reshape(5))
+    return lib().orc_wenoz(_p(v))
 
 
 def glm_interface(bnL, bnR, psiL, psiR, ch):

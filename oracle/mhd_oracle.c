@@ -12,13 +12,20 @@
  * HLLD and, for strong scaling, GLM divergence cleaning).  The paper prints
  * no equations, so each step below follows the published method it names:
  *
- *   ghosts   : 2 layers per active face, periodic wrap or zero-gradient
+ *   ghosts   : 3 layers per active face, periodic wrap or zero-gradient
  *              copy of the nearest interior cell (all 9 components).
  *   prim     : rho, v = m/rho, p = (gamma-1)(E - |m|^2/(2 rho) - |B|^2/2),
  *              B, psi.  Units with magnetic pressure |B|^2/2.  No floors:
  *              rho <= 0, p <= 0 or a non-finite value is an error.
  *   PLM      : piecewise-linear (van Leer 1979) reconstruction of the 9
  *              primitives, component-wise, minmod (or MC) limited slope.
+ *   WENO-Z   : (the paper's benchmark reconstruction, section "Results for
+ *              gPLUTO") fifth-order WENO-Z of Borges, Carmona, Costa & Don
+ *              (2008), component-wise on the primitives: three third-order
+ *              candidate values, Jiang-Shu smoothness indicators, global
+ *              indicator tau5 = |beta0 - beta2|, weights
+ *              alpha_k = d_k (1 + tau5 / (beta_k + eps)), d = (1, 6, 3)/10,
+ *              eps = 1e-40.
  *   GLM      : Dedner et al. (2002) mixed GLM: the (B_n, psi) 2x2 system is
  *              solved exactly at each interface before the MHD solver.
  *   Riemann  : HLL (Harten, Lax & van Leer 1983) or HLLD (Miyoshi & Kusano
@@ -26,6 +33,9 @@
  *   RHS      : L = -sum_d (F_{i+1/2} - F_{i-1/2}) / dx_d, d = x, y, z.
  *   RK2      : SSP-RK2 (Shu & Osher 1988): U1 = Un + dt L(Un);
  *              Un+1 = (Un + U1 + dt L(U1)) / 2, dt and c_h fixed per step.
+ *   RK3      : (the paper's benchmark integrator) SSP-RK3 (Shu & Osher
+ *              1988): U1 = Un + dt L(Un); U2 = 3/4 Un + 1/4 (U1 + dt L(U1));
+ *              Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)).
  *   damping  : psi <- psi * damp once per step after the RK2 update, with
  *              damp = exp(-alpha c_h dt / dh_min) supplied by the caller.
  *   CFL      : dt = C / max_{cells,d} (|v_d| + c_f,d) / dx_d,
@@ -51,7 +61,7 @@ enum { RHO = 0, VX = 1, VY = 2, VZ = 3, PRS = 4, BX = 5, BY = 6, BZ = 7, PSI = 8
 enum { MX = 1, MY = 2, MZ = 3, ENG = 4 };
 
 enum { ORC_HLL = 0, ORC_HLLD = 1 };
-enum { ORC_MINMOD = 0, ORC_MC = 1 };
+enum { ORC_MINMOD = 0, ORC_MC = 1, ORC_WENOZ = 2 };
 enum { ORC_PERIODIC = 0, ORC_OUTFLOW = 1 };
 
 typedef struct {
@@ -66,6 +76,8 @@ typedef struct {
     double gamma;
     double cfl;
     double glm_alpha;
+    int32_t time_order; /* 2: SSP-RK2, 3: SSP-RK3 */
+    int32_t reserved;
 } orc_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -150,6 +162,29 @@ static double limited_slope(int limiter, double a, double b)
         m = fmin(2.0 * m, 0.5 * fabs(a + b));
     }
     return s * m;
+}
+
+/* WENO-Z value at the right face of the middle cell of v[0..4] (cells
+ * i-2 .. i+2); the left face value of cell i is the same function of the
+ * mirrored stencil. */
+static double wenoz(const double *v)
+{
+    const double q0 = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) / 6.0;
+    const double q1 = (-v[1] + 5.0 * v[2] + 2.0 * v[3]) / 6.0;
+    const double q2 = (2.0 * v[2] + 5.0 * v[3] - v[4]) / 6.0;
+    const double c = 13.0 / 12.0;
+    const double b0 = c * (v[0] - 2.0 * v[1] + v[2]) * (v[0] - 2.0 * v[1] + v[2]) +
+                      0.25 * (v[0] - 4.0 * v[1] + 3.0 * v[2]) * (v[0] - 4.0 * v[1] + 3.0 * v[2]);
+    const double b1 = c * (v[1] - 2.0 * v[2] + v[3]) * (v[1] - 2.0 * v[2] + v[3]) +
+                      0.25 * (v[1] - v[3]) * (v[1] - v[3]);
+    const double b2 = c * (v[2] - 2.0 * v[3] + v[4]) * (v[2] - 2.0 * v[3] + v[4]) +
+                      0.25 * (3.0 * v[2] - 4.0 * v[3] + v[4]) * (3.0 * v[2] - 4.0 * v[3] + v[4]);
+    const double tau = fabs(b0 - b2);
+    const double eps = 1e-40;
+    const double a0 = 0.1 * (1.0 + tau / (b0 + eps));
+    const double a1 = 0.6 * (1.0 + tau / (b1 + eps));
+    const double a2 = 0.3 * (1.0 + tau / (b2 + eps));
+    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
 /* The rotated frame used by the one-dimensional solvers: for a face normal
@@ -429,7 +464,7 @@ static void face_flux(const orc_cfg *cfg, int d, const double *VL, const double 
 
 typedef struct {
     int64_t n[3];   /* interior cells */
-    int64_t g[3];   /* ghost width: 2 on active axes, 0 otherwise */
+    int64_t g[3];   /* ghost width: 3 on active axes, 0 otherwise */
     int64_t N[3];   /* padded extents */
     int64_t cells;  /* padded cell count */
 } grid;
@@ -438,7 +473,7 @@ static void grid_make(const orc_cfg *cfg, grid *G)
 {
     for (int d = 0; d < 3; ++d) {
         G->n[d] = cfg->n[d];
-        G->g[d] = d < cfg->ndim ? 2 : 0;
+        G->g[d] = d < cfg->ndim ? 3 : 0;
         G->N[d] = G->n[d] + 2 * G->g[d];
     }
     G->cells = G->N[0] * G->N[1] * G->N[2];
@@ -462,11 +497,11 @@ static void fill_ghosts(const orc_cfg *cfg, const grid *G, double *W)
         for (int64_t b = lo2; b < hi2; ++b) {
             for (int64_t a = lo1; a < hi1; ++a) {
                 for (int side = 0; side < 2; ++side) {
-                    for (int layer = 1; layer <= 2; ++layer) {
+                    for (int layer = 1; layer <= G->g[d]; ++layer) {
                         int64_t dst = side == 0 ? -layer : n - 1 + layer;
                         int64_t src;
                         if (cfg->bc[d][side] == ORC_PERIODIC)
-                            src = side == 0 ? n - layer : layer - 1;
+                            src = ((dst % n) + n) % n;
                         else
                             src = side == 0 ? 0 : n - 1;
                         int64_t c[3], s[3];
@@ -529,12 +564,22 @@ static void rhs_from_prims(const orc_cfg *cfg, const grid *G, const double *W, d
                         const double *B = A + stride;                     /* right cell */
                         double VL[NV], VR[NV];
                         for (int q = 0; q < NV; ++q) {
-                            double sa = limited_slope(cfg->limiter, A[q] - A[q - stride],
-                                                      B[q] - A[q]);
-                            double sb = limited_slope(cfg->limiter, B[q] - A[q],
-                                                      B[q + stride] - B[q]);
-                            VL[q] = A[q] + 0.5 * sa;
-                            VR[q] = B[q] - 0.5 * sb;
+                            if (cfg->limiter == ORC_WENOZ) {
+                                double sa[5], sb[5];
+                                for (int m = 0; m < 5; ++m) {
+                                    sa[m] = A[q + (m - 2) * stride];  /* cells A-2 .. A+2 */
+                                    sb[m] = B[q + (2 - m) * stride];  /* cells B+2 .. B-2 */
+                                }
+                                VL[q] = wenoz(sa);
+                                VR[q] = wenoz(sb);
+                            } else {
+                                double sa = limited_slope(cfg->limiter, A[q] - A[q - stride],
+                                                          B[q] - A[q]);
+                                double sb = limited_slope(cfg->limiter, B[q] - A[q],
+                                                          B[q + stride] - B[q]);
+                                VL[q] = A[q] + 0.5 * sa;
+                                VR[q] = B[q] - 0.5 * sb;
+                            }
                         }
                         face_flux(cfg, d, VL, VR, ch, face == 0 ? Fm : Fp);
                     }
@@ -569,6 +614,8 @@ static int cfg_ok(const orc_cfg *cfg)
         if (d >= cfg->ndim && cfg->n[d] != 1) return 0;
         if (d < cfg->ndim && !(cfg->hi[d] > cfg->lo[d])) return 0;
     }
+    if (cfg->limiter < ORC_MINMOD || cfg->limiter > ORC_WENOZ) return 0;
+    if (cfg->time_order != 2 && cfg->time_order != 3) return 0;
     return cfg->gamma > 1.0;
 }
 
@@ -641,7 +688,8 @@ int orc_rhs(const orc_cfg *cfg, const double *U, double ch, double *L)
     return rhs(cfg, U, ch, L);
 }
 
-/* One SSP-RK2 step with GLM damping.  U1_out may be NULL. */
+/* One SSP-RK2 or SSP-RK3 step with GLM damping.  U1_out (the first stage
+ * state) may be NULL. */
 int orc_step(const orc_cfg *cfg, const double *Un, double *Unext, double *U1_out, double dt,
              double ch, double damp)
 {
@@ -660,7 +708,19 @@ int orc_step(const orc_cfg *cfg, const double *Un, double *Unext, double *U1_out
         for (int64_t a = 0; a < nt; ++a) U1[a] = Un[a] + dt * L[a];
         st = rhs(cfg, U1, ch, L);
     }
-    if (st == 0) {
+    if (st == 0 && cfg->time_order == 3) {
+        if (U1_out) memcpy(U1_out, U1, sizeof(double) * nt);
+        /* U2 = 3/4 Un + 1/4 (U1 + dt L(U1)), stored over U1 */
+#pragma omp parallel for schedule(static)
+        for (int64_t a = 0; a < nt; ++a) U1[a] = 0.75 * Un[a] + 0.25 * (U1[a] + dt * L[a]);
+        st = rhs(cfg, U1, ch, L);
+        if (st == 0) {
+#pragma omp parallel for schedule(static)
+            for (int64_t a = 0; a < nt; ++a)
+                Unext[a] = Un[a] / 3.0 + 2.0 / 3.0 * (U1[a] + dt * L[a]);
+            for (int64_t c = 0; c < nc; ++c) Unext[PSI * nc + c] *= damp;
+        }
+    } else if (st == 0) {
 #pragma omp parallel for schedule(static)
         for (int64_t a = 0; a < nt; ++a) Unext[a] = 0.5 * (Un[a] + U1[a] + dt * L[a]);
         for (int64_t c = 0; c < nc; ++c) Unext[PSI * nc + c] *= damp;
@@ -699,6 +759,8 @@ int orc_sums(const orc_cfg *cfg, const double *U, double *out)
 double orc_fast_speed(const double *V, double gamma, int d) { return fast_speed(V, gamma, d); }
 
 double orc_limited_slope(int limiter, double a, double b) { return limited_slope(limiter, a, b); }
+
+double orc_wenoz(const double *v) { return wenoz(v); }
 
 void orc_glm_interface(double bnL, double bnR, double psiL, double psiR, double ch, double *out)
 {

@@ -32,13 +32,16 @@ OUTFLOW_X = (("outflow", "outflow"), ("periodic", "periodic"), ("periodic", "per
 
 def make_setup(name, ndim, n, *, gamma, cfl, riemann="hlld", limiter="minmod", bc=PERIODIC3,
                glm=True, glm_alpha=0.1, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), nsteps=None,
-               t_end=None):
+               t_end=None, time_order=2):
+    """A problem setup.  limiter: "minmod" or "mc" (PLM) or "wenoz" (the
+    fifth-order WENO-Z reconstruction); time_order 2 (SSP-RK2) or 3
+    (SSP-RK3)."""
     n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
     return {
         "name": name, "ndim": int(ndim), "n": n, "lo": tuple(lo), "hi": tuple(hi),
         "gamma": float(gamma), "cfl": float(cfl), "riemann": riemann, "limiter": limiter,
         "bc": tuple(tuple(b) for b in bc), "glm": bool(glm), "glm_alpha": float(glm_alpha),
-        "nsteps": nsteps, "t_end": t_end,
+        "nsteps": nsteps, "t_end": t_end, "time_order": int(time_order),
     }
 
 

@@ -1,0 +1,231 @@
+"""Pins of the oracle's WENO-Z reconstruction and SSP-RK3 integrator (the
+paper's benchmark configuration, section "Results for gPLUTO").
+
+Reconstruction (Borges, Carmona, Costa & Don 2008):
+* exact for the cell averages of any quadratic (every candidate stencil is,
+  and the weights are convex) - catches a wrong candidate coefficient;
+* fifth-order accurate on smooth data (error ratio ~32 per halving), which
+  needs the linear weights (1, 6, 3)/10 and smoothness indicators whose
+  difference tau5 is O(h^5) - a wrong weight or indicator drops it to ~3;
+* on a step it takes the smooth candidate (no value beyond the data range);
+* constant data is reproduced exactly (eps only guards 0/0);
+* on rough random data it equals WENO-Z rebuilt from the definitions
+  (candidate quadratics fitted to cell averages, smoothness indicators as
+  integrals of the squared derivatives, linear weights from the quartic
+  fit) - catches a wrong indicator or global indicator.
+Integrator (Shu & Osher 1988):
+* temporal order 3 on a fixed grid (error ratio ~8 per halving of dt),
+  against order 2 for SSP-RK2 - a wrong stage coefficient drops it to 1 or 2.
+Scheme (WENO-Z + HLLD + GLM + SSP-RK3):
+* uniform states are fixed points (bitwise with SSP-RK2, to rounding with
+  the convex SSP-RK3 combinations); periodic conservation; mirror
+  symmetry; the circularly polarised Alfven wave converges at third order
+  when dt shrinks with h (RK3-limited).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import coracle as C
+from paper_2510_24175_amd import workloads as W
+
+
+def _avg_poly(coef, xl, xr):
+    """Cell average of sum_k coef[k] x^k over [xl, xr]."""
+    s = 0.0
+    for k, c in enumerate(coef):
+        s += c * (xr ** (k + 1) - xl ** (k + 1)) / (k + 1)
+    return s / (xr - xl)
+
+
+def _poly(coef, x):
+    return sum(c * x ** k for k, c in enumerate(coef))
+
+
+def test_wenoz_exact_for_quadratics():
+    rng = np.random.default_rng(21)
+    for _ in range(50):
+        coef = rng.normal(size=3)
+        h = 10 ** rng.uniform(-3, 0)
+        x0 = rng.uniform(-1, 1)
+        v = [_avg_poly(coef, x0 + (m - 3) * h, x0 + (m - 2) * h) for m in range(5)]
+        exact = _poly(coef, x0)  # right face of the middle cell
+        scale = max(abs(c) for c in coef) * (1 + abs(x0)) ** 2
+        assert abs(C.wenoz(v) - exact) <= 1e-12 * scale
+
+
+def test_wenoz_fifth_order_on_smooth_data():
+    def err(h, x0):
+        v = [(math.cos(x0 + (m - 3) * h) - math.cos(x0 + (m - 2) * h)) / h for m in range(5)]
+        return abs(C.wenoz(v) - math.sin(x0))
+
+    for x0 in (0.3, 1.1, 2.0):
+        e = [err(h, x0) for h in (0.1, 0.05, 0.025)]
+        orders = [math.log2(e[0] / e[1]), math.log2(e[1] / e[2])]
+        assert min(orders) >= 4.5, (x0, e)
+
+
+def _wenoz_from_definitions(v, h=1.0):
+    """WENO-Z built from its definitions, not from the closed-form
+    coefficients: candidate k is the quadratic whose averages over cells
+    k-2 .. k (relative to the middle cell 0 = [-h, 0]) are the data; its
+    smoothness indicator is sum_{l=1,2} h^(2l-1) int_cell (d^l p/dx^l)^2 dx;
+    the linear weights make the combination equal the quartic fitted to all
+    five averages; tau5 = |beta_0 - beta_2|, alpha_k = d_k (1 + tau5 /
+    (beta_k + 1e-40)).  The value is taken at the middle cell's right face x = 0."""
+    edges = [(m - 3) * h for m in range(6)]  # cells [-3h,-2h] .. [h,2h]
+
+    def fit(cells, deg):
+        A = np.array([[(edges[c + 1] ** (p + 1) - edges[c] ** (p + 1)) / ((p + 1) * h)
+                       for p in range(deg + 1)] for c in cells])
+        return np.linalg.solve(A, np.array([v[c] for c in cells]))
+
+    polys = [fit([k, k + 1, k + 2], 2) for k in range(3)]
+    q = np.array([c[0] for c in polys])  # p(0)
+    quartic = fit([0, 1, 2, 3, 4], 4)
+    # linear weights: d . q(any data) = quartic(0) for every quartic; use the
+    # five monomial data sets to solve for d (overdetermined, exact)
+    rows, rhs = [], []
+    for p in range(5):
+        mono = [(edges[c + 1] ** (p + 1) - edges[c] ** (p + 1)) / ((p + 1) * h) for c in range(5)]
+        qk = []
+        for k in range(3):
+            A = np.array([[(edges[c + 1] ** (r + 1) - edges[c] ** (r + 1)) / ((r + 1) * h)
+                           for r in range(3)] for c in (k, k + 1, k + 2)])
+            qk.append(np.linalg.solve(A, np.array([mono[k], mono[k + 1], mono[k + 2]]))[0])
+        rows.append(qk)
+        rhs.append(1.0 if p == 0 else 0.0)  # x^p at x = 0
+    d = np.linalg.lstsq(np.array(rows), np.array(rhs), rcond=None)[0]
+    beta = []
+    x1, x2 = -h, 0.0  # the middle cell
+    for c0, c1, c2 in polys:
+        # p' = c1 + 2 c2 x, p'' = 2 c2
+        int_d1 = (c1 ** 2 * (x2 - x1) + 2 * c1 * c2 * (x2 ** 2 - x1 ** 2)
+                  + 4 * c2 ** 2 * (x2 ** 3 - x1 ** 3) / 3)
+        int_d2 = 4 * c2 ** 2 * (x2 - x1)
+        beta.append(h * int_d1 + h ** 3 * int_d2)
+    beta = np.array(beta)
+    tau = abs(beta[0] - beta[2])
+    alpha = d * (1 + tau / (beta + 1e-40))
+    return float((alpha * q).sum() / alpha.sum()), d, (quartic, float(np.dot(d, q)))
+
+
+def test_wenoz_matches_its_definitions_on_rough_data():
+    _, d, _ = _wenoz_from_definitions([0.0, 1.0, 0.0, 2.0, 1.0])
+    np.testing.assert_allclose(d, [0.1, 0.6, 0.3], rtol=1e-12)
+    rng = np.random.default_rng(22)
+    for _ in range(200):
+        v = rng.normal(size=5) * 10 ** rng.uniform(-3, 3) + rng.normal() * 10 ** rng.uniform(-3, 3)
+        ref = _wenoz_from_definitions(v)[0]
+        got = C.wenoz(v)
+        assert abs(got - ref) <= 1e-11 * (np.abs(v).max() + 1e-300), (v, got, ref)
+
+
+def test_wenoz_takes_the_smooth_stencil_at_a_step():
+    assert abs(C.wenoz([0.0, 0.0, 0.0, 1.0, 1.0])) <= 1e-30
+    assert abs(C.wenoz([1.0, 1.0, 1.0, 0.0, 0.0]) - 1.0) <= 1e-30
+    v = C.wenoz([0.0, 0.0, 1.0, 1.0, 1.0])
+    assert 1.0 - 1e-12 <= v <= 1.0 + 1e-12
+
+
+def test_wenoz_reproduces_constants():
+    for c in (0.0, 1.0, -3.5, 1e-20, 7e5):
+        assert C.wenoz([c] * 5) == c
+
+
+def _cpa_setup(n, cfl, time_order, limiter="wenoz"):
+    s, V = W.cpa_wave((n,), amplitude=0.1, cfl=cfl)
+    s["limiter"] = limiter
+    s["time_order"] = time_order
+    return s, V
+
+
+def _fixed_dt_run(setup, V, nsteps, t_end):
+    o = C.Oracle(setup)
+    U = o.prim_to_cons(V)
+    _, ch = o.cfl(U)
+    dt = t_end / nsteps
+    for _ in range(nsteps):
+        U = o.step(U, dt, ch, 1.0)
+    return U
+
+
+@pytest.mark.parametrize("time_order,expect", [(3, 3.0), (2, 2.0)])
+def test_temporal_order(time_order, expect):
+    # fixed grid: the method-of-lines ODE system is integrated with shrinking
+    # dt; errors against a 16x finer dt
+    s, V = _cpa_setup(32, 0.4, time_order)
+    t_end = 0.25
+    ref = _fixed_dt_run(s, V, 320, t_end)
+    e = [np.abs(_fixed_dt_run(s, V, m, t_end) - ref).max() for m in (20, 40, 80)]
+    orders = [math.log2(e[0] / e[1]), math.log2(e[1] / e[2])]
+    assert min(orders) >= expect - 0.3 and max(orders) <= expect + 0.5, e
+
+
+@pytest.mark.parametrize("time_order", [2, 3])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_uniform_state_is_a_fixed_point(ndim, time_order):
+    # WENO-Z returns constants exactly and the fluxes cancel, so with SSP-RK2
+    # ((a + a)/2 = a) the state is kept bit for bit; the convex SSP-RK3
+    # combinations 3/4 a + 1/4 a and 1/3 a + 2/3 a round to within an ulp
+    n = {1: (16,), 2: (8, 6), 3: (6, 5, 4)}[ndim]
+    s, V = W.uniform(n, ndim=ndim)
+    s["limiter"], s["time_order"] = "wenoz", time_order
+    o = C.Oracle(s)
+    U0 = o.prim_to_cons(V)
+    U, _, _ = o.run(U0, nsteps=50)
+    if time_order == 2:
+        np.testing.assert_array_equal(U, U0)
+    else:
+        np.testing.assert_allclose(U, U0, rtol=1e-14, atol=0)
+
+
+def test_periodic_conservation():
+    s, V = W.turbulence(12)
+    s["limiter"], s["time_order"] = "wenoz", 3
+    o = C.Oracle(s)
+    U0 = o.prim_to_cons(V)
+    U, _, _ = o.run(U0, nsteps=20)
+    scale = np.array([np.abs(U0[q]).sum() for q in range(9)]) * o.cell_volume
+    rel = np.abs(o.sums(U) - o.sums(U0))[:8] / scale[:8]
+    assert rel.max() <= 1e-13, rel
+
+
+def test_mirror_symmetry():
+    s, V = W.turbulence(12)
+    s["limiter"], s["time_order"] = "wenoz", 3
+    o = C.Oracle(s)
+    U0 = o.prim_to_cons(V)
+    M = U0[:, :, :, ::-1].copy()
+    M[1] *= -1
+    M[5] *= -1
+    hist = o.run(U0, nsteps=10)[2]
+    A = o.replay(U0, hist)
+    B = o.replay(M, hist)[:, :, :, ::-1].copy()
+    B[1] *= -1
+    B[5] *= -1
+    scale = np.abs(A).max(axis=(1, 2, 3), keepdims=True) + 1e-300
+    assert (np.abs(A - B) / scale)[:8].max() <= 1e-13
+
+
+def test_alfven_wave_third_order():
+    def err(n):
+        s, V = W.cpa_wave((n,), amplitude=0.1, cfl=0.4)
+        s["limiter"], s["time_order"] = "wenoz", 3
+        o = C.Oracle(s)
+        U, _, _ = o.run(o.prim_to_cons(V), t_end=s["period"])
+        Vf = o.cons_to_prim(U)
+        comps = [1, 2, 3, 5, 6, 7]
+        return np.mean(np.abs(Vf[comps] - V[comps]))
+
+    e = [err(n) for n in (16, 32, 64)]
+    order = math.log2(e[1] / e[2])
+    assert order >= 2.7, e
+    # and much smaller than PLM + RK2 at the same grid
+    s, V = W.cpa_wave((64,), amplitude=0.1, cfl=0.4)
+    o = C.Oracle(s)
+    U, _, _ = o.run(o.prim_to_cons(V), t_end=s["period"])
+    Vf = o.cons_to_prim(U)
+    e_plm = np.mean(np.abs(Vf[[1, 2, 3, 5, 6, 7]] - V[[1, 2, 3, 5, 6, 7]]))
+    assert e[2] <= 0.1 * e_plm, (e[2], e_plm)
