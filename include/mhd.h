@@ -3,22 +3,26 @@
  *
  * One call of mhd_step advances the conserved state
  *     U = (rho, m_x, m_y, m_z, E, B_x, B_y, B_z, psi)
- * on a uniform Cartesian grid by one second-order Runge-Kutta step of a
- * Godunov-type finite-volume scheme.  The paper (section "Porting of
+ * on a uniform Cartesian grid by one strong-stability-preserving
+ * Runge-Kutta step of a Godunov-type finite-volume scheme.  The paper (section "Porting of
  * gPLUTO") lists the steps repeated in every Runge-Kutta stage: boundary
  * (ghost-zone) calculation, conservative -> primitive map, reconstruction of
  * interface values, Riemann fluxes, right-hand side; plus one
  * divergence-control algorithm, here GLM divergence cleaning (section
  * "Results for gPLUTO", strong-scaling runs).  The paper prints no
  * formulas; the operations follow the published methods it names or uses:
- *   - ghosts: 2 layers per active face, periodic or zero-gradient outflow;
- *   - reconstruction: piecewise linear in the primitive variables,
- *     component-wise, minmod or MC limited (van Leer 1979);
+ *   - ghosts: 2 layers per active face (3 with WENO-Z), periodic or
+ *     zero-gradient outflow;
+ *   - reconstruction, component-wise in the primitive variables: piecewise
+ *     linear, minmod or MC limited (van Leer 1979), or fifth-order WENO-Z
+ *     (Borges et al. 2008; p = 1, eps = 1e-40 in FP64, 1e-30 in FP32), the
+ *     scheme of the paper's benchmark runs (section "Results for gPLUTO");
  *   - GLM: Dedner et al. (2002) mixed GLM, exact (B_n, psi) interface
  *     solve, psi damped by exp(-alpha c_h dt / dh_min) once per step;
  *   - Riemann: HLL (Harten, Lax & van Leer 1983) or HLLD (Miyoshi & Kusano
  *     2005) with Davis wave-speed bounds;
- *   - time: SSP-RK2 (Shu & Osher 1988), dt and c_h fixed for the step;
+ *   - time: SSP-RK2 or SSP-RK3 (Shu & Osher 1988; RK3 is the benchmark
+ *     integrator of the paper), dt and c_h fixed for the step;
  *   - CFL: dt = C / max_{cells,d} (|v_d| + c_f,d)/dx_d and
  *     c_h = max_{cells,d} (|v_d| + c_f,d), reduced in FP64.
  * Magnetic pressure is |B|^2/2; ideal gas E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2
@@ -33,7 +37,8 @@
  *
  * Ownership: the caller owns every state, adjoint and primitive buffer.
  * The library owns the context and its scratch (stage-1 buffer when the
- * caller passes none, reduction partials, result and error words), all
+ * caller passes none, the SSP-RK3 stage-2 buffer, reduction partials,
+ * result and error words), all
  * allocated by mhd_init and freed by mhd_destroy; mhd_step,
  * mhd_step_adjoint and mhd_cfl_dt allocate nothing.
  *
@@ -70,18 +75,19 @@ typedef enum {
 
 enum { MHD_F32 = 0, MHD_F64 = 1 };       /* storage and bulk arithmetic */
 enum { MHD_HLL = 0, MHD_HLLD = 1 };      /* Riemann solver              */
-enum { MHD_MINMOD = 0, MHD_MC = 1 };     /* slope limiter               */
+enum { MHD_MINMOD = 0, MHD_MC = 1, MHD_WENOZ = 2 }; /* reconstruction */
 enum { MHD_PERIODIC = 0, MHD_OUTFLOW = 1 }; /* boundary per face        */
 /* MHD_FLAG_ADJOINT: mhd_init also allocates the adjoint scratch (an FP64
- * stage cotangent, 9 doubles per cell, and per-face contributions, 36 state
- * elements per face and axis); mhd_step_adjoint needs it. */
+ * stage cotangent, 9 doubles per cell); mhd_step_adjoint needs it.  The
+ * adjoint covers the PLM reconstructions with SSP-RK2 only: with WENO-Z or
+ * SSP-RK3 mhd_init returns MHD_ERR_UNSUPPORTED for this flag. */
 enum { MHD_FLAG_ADJOINT = 1 };
 
 typedef struct {
     int32_t ndim;      /* 1, 2 or 3; axes >= ndim must have n = 1            */
     int32_t dtype;     /* MHD_F32 or MHD_F64                                 */
     int32_t riemann;   /* MHD_HLL or MHD_HLLD                                */
-    int32_t limiter;   /* MHD_MINMOD or MHD_MC                               */
+    int32_t limiter;   /* MHD_MINMOD, MHD_MC (PLM) or MHD_WENOZ              */
     int64_t n[3];      /* interior cells nx, ny, nz; n >= 2 on active axes   */
     double lo[3];      /* domain lower corner                                */
     double hi[3];      /* domain upper corner; dx_d = (hi-lo)/n              */
@@ -91,14 +97,17 @@ typedef struct {
     double gamma;      /* adiabatic index > 1                                */
     double cfl;        /* Courant number C in (0, 1]                         */
     double glm_alpha;  /* GLM damping parameter alpha >= 0                   */
+    int32_t time_order; /* 2: SSP-RK2, 3: SSP-RK3                            */
+    int32_t reserved;  /* must be 0                                          */
 } mhd_config;
 
 /* Create a context for one grid on the current HIP device.  hip_stream is a
  * hipStream_t (NULL = the null stream).  Allocates the library scratch.
  * Returns MHD_ERR_ARG for an invalid config (bad ndim, n, bounds, dtype,
- * solver, limiter, mixed periodic/outflow on one axis, gamma <= 1, cfl not
- * in (0,1], glm_alpha < 0), MHD_ERR_NO_DEVICE when no gfx950 device is
- * current.  *out is NULL on failure. */
+ * solver, limiter, time_order, reserved != 0, mixed periodic/outflow on one
+ * axis, gamma <= 1, cfl not in (0,1], glm_alpha < 0), MHD_ERR_UNSUPPORTED
+ * for MHD_FLAG_ADJOINT with WENO-Z or SSP-RK3, MHD_ERR_NO_DEVICE when no
+ * gfx950 device is current.  *out is NULL on failure. */
 mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out);
 
 /* Release the context and its scratch (syncs).  NULL is ignored. */
@@ -119,10 +128,15 @@ mhd_status mhd_prim_to_cons(mhd_ctx *ctx, const double *V, void *U);
  * MHD_ERR_NONPHYSICAL if any cell is non-physical. */
 mhd_status mhd_cfl_dt(mhd_ctx *ctx, const void *U, double out[2]);
 
-/* One SSP-RK2 step (async):
+/* One Runge-Kutta step (async).  SSP-RK2 (time_order 2):
  *   U1     = Un + dt L(Un)
- *   U_next = (Un + U1 + dt L(U1)) / 2,  then psi <- psi * damp
- * with L the flux divergence built with the given c_h.  U_next must not
+ *   U_next = (Un + U1 + dt L(U1)) / 2,  then psi <- psi * damp;
+ * SSP-RK3 (time_order 3):
+ *   U1     = Un + dt L(Un)
+ *   U2     = 3/4 Un + 1/4 (U1 + dt L(U1))
+ *   U_next = 1/3 Un + 2/3 (U2 + dt L(U2)),  then psi <- psi * damp;
+ * with L the flux divergence built with the given c_h (U2 lives in library
+ * scratch).  U_next must not
  * alias Un.  U1_out (may be NULL) receives the stage-1 state, which the
  * adjoint reuses; otherwise library scratch is used.  The step also
  * reduces, on U_next, the CFL maxima and the FP64 sums read back by
@@ -162,11 +176,13 @@ mhd_status mhd_prim_to_cons_adjoint(mhd_ctx *ctx, const double *V, const double 
 /* Kernel timing with HIP events on the context stream.  mhd_timing_start
  * creates 4 events per step for up to `capacity` later mhd_step calls
  * (the only allocation, made here) and starts recording; each mhd_step
- * then records an event before its stage-1 kernel, between the two stage
- * kernels, after stage 2 and after the final reduction.  mhd_timing_stop
+ * then records an event before its first stage kernel, before its last
+ * stage kernel, after it and after the final reduction.  mhd_timing_stop
  * (syncs) returns out[0] = steps recorded, out[1..3] = total milliseconds
- * of the stage-1 kernel, the stage-2 kernel and the final reduction over
- * those steps, then frees the events.  Steps beyond capacity are not timed. */
+ * of the stage kernels before the last one (one with SSP-RK2, two with
+ * SSP-RK3), the last stage kernel (which also reduces the CFL maxima and
+ * sums) and the final reduction over those steps, then frees the events.
+ * Steps beyond capacity are not timed. */
 mhd_status mhd_timing_start(mhd_ctx *ctx, int32_t capacity);
 mhd_status mhd_timing_stop(mhd_ctx *ctx, double out[4]);
 

@@ -25,6 +25,7 @@ struct mhd_ctx {
     long long ncell = 0;
     size_t elem = 4;             // bytes per state element
     void *u1_scratch = nullptr;  // stage-1 state when the caller passes none
+    void *u2_scratch = nullptr;  // SSP-RK3 stage-2 state
     double *part = nullptr;      // NPART x part_cap block partials
     int part_cap = 0;
     double *result = nullptr;    // device NPART doubles
@@ -77,7 +78,7 @@ Launch plan_stage(const mhd_ctx *ctx, int ty)
     const long long tiles = (long long)L.tiles_x * L.tiles_y;
     int kz = 1;
     if (ctx->cfg.ndim == 3) {
-        // long z chunks amortise the 4-plane warm-up; shorter chunks when
+        // long z chunks amortise the warm-up planes; shorter chunks when
         // the grid would otherwise leave compute units idle
         kz = 64;
         while (kz > 4 && tiles * ((ctx->n[2] + kz - 1) / kz) < 2048) kz >>= 1;
@@ -105,6 +106,7 @@ template <typename T> Phys<T> make_phys(const mhd_ctx *ctx, double ch)
 template <typename T, int SOLVER, int LIM, int NDIM>
 mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, double ch, double damp)
 {
+    const bool rk3 = ctx->cfg.time_order == 3;
     constexpr int TY = tile_rows<T, NDIM>();
     const Launch L = plan_stage(ctx, TY);
     if (L.nblocks > ctx->part_cap) return fail(ctx, MHD_ERR_ARG, "grid too large for partials buffer");
@@ -140,13 +142,27 @@ mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, do
     hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 1, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
                        ctx->stream, a);
     HIP_TRY(ctx, hipGetLastError());
-    if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
-    a.uin = u1;
-    a.un = un;
-    a.uout = unext;
-    hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 2, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
-                       ctx->stream, a);
-    HIP_TRY(ctx, hipGetLastError());
+    if (rk3) {
+        T *u2 = (T *)ctx->u2_scratch;
+        a.uin = u1;
+        a.uout = u2;
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 3, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+                           ctx->stream, a);
+        HIP_TRY(ctx, hipGetLastError());
+        if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
+        a.uin = u2;
+        a.uout = unext;
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 4, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+                           ctx->stream, a);
+        HIP_TRY(ctx, hipGetLastError());
+    } else {
+        if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
+        a.uin = u1;
+        a.uout = unext;
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 2, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+                           ctx->stream, a);
+        HIP_TRY(ctx, hipGetLastError());
+    }
     if (ev) HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
     hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(RED_THREADS), 0, ctx->stream,
                        (const double *)ctx->part, L.nblocks, ctx->result);
@@ -278,16 +294,21 @@ template <typename T_, int SOLVER_, int LIM_> struct Scheme {
     static constexpr int LIM = LIM_;
 };
 
+template <typename T, int SOLVER, typename Fn> mhd_status with_recon(const mhd_ctx *ctx, Fn &&fn)
+{
+    switch (ctx->cfg.limiter) {
+    case MHD_MC: return fn(Scheme<T, SOLVER, LIM_MC>{});
+    case MHD_WENOZ: return fn(Scheme<T, SOLVER, LIM_WENOZ>{});
+    default: return fn(Scheme<T, SOLVER, LIM_MINMOD>{});
+    }
+}
+
 template <typename Fn> mhd_status with_scheme(const mhd_ctx *ctx, Fn &&fn)
 {
-    const bool mc = ctx->cfg.limiter == MHD_MC;
     const bool hlld = ctx->cfg.riemann == MHD_HLLD;
-    if (ctx->cfg.dtype == MHD_F32) {
-        if (hlld) return mc ? fn(Scheme<float, SOLVER_HLLD, LIM_MC>{}) : fn(Scheme<float, SOLVER_HLLD, LIM_MINMOD>{});
-        return mc ? fn(Scheme<float, SOLVER_HLL, LIM_MC>{}) : fn(Scheme<float, SOLVER_HLL, LIM_MINMOD>{});
-    }
-    if (hlld) return mc ? fn(Scheme<double, SOLVER_HLLD, LIM_MC>{}) : fn(Scheme<double, SOLVER_HLLD, LIM_MINMOD>{});
-    return mc ? fn(Scheme<double, SOLVER_HLL, LIM_MC>{}) : fn(Scheme<double, SOLVER_HLL, LIM_MINMOD>{});
+    if (ctx->cfg.dtype == MHD_F32)
+        return hlld ? with_recon<float, SOLVER_HLLD>(ctx, fn) : with_recon<float, SOLVER_HLL>(ctx, fn);
+    return hlld ? with_recon<double, SOLVER_HLLD>(ctx, fn) : with_recon<double, SOLVER_HLL>(ctx, fn);
 }
 
 template <typename T>
@@ -335,13 +356,18 @@ mhd_status sync_results(mhd_ctx *ctx)
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+// Validates a configuration: MHD_ERR_ARG for invalid fields,
+// MHD_ERR_UNSUPPORTED for the adjoint of WENO-Z or SSP-RK3 (not built).
 mhd_status check_config(const mhd_config *c, std::string &why)
 {
     if (!c) return why = "config is NULL", MHD_ERR_ARG;
     if (c->ndim < 1 || c->ndim > 3) return why = "ndim must be 1, 2 or 3", MHD_ERR_ARG;
     if (c->dtype != MHD_F32 && c->dtype != MHD_F64) return why = "bad dtype", MHD_ERR_ARG;
     if (c->riemann != MHD_HLL && c->riemann != MHD_HLLD) return why = "bad riemann", MHD_ERR_ARG;
-    if (c->limiter != MHD_MINMOD && c->limiter != MHD_MC) return why = "bad limiter", MHD_ERR_ARG;
+    if (c->limiter != MHD_MINMOD && c->limiter != MHD_MC && c->limiter != MHD_WENOZ)
+        return why = "bad limiter", MHD_ERR_ARG;
+    if (c->time_order != 2 && c->time_order != 3) return why = "time_order must be 2 or 3", MHD_ERR_ARG;
+    if (c->reserved != 0) return why = "reserved must be 0", MHD_ERR_ARG;
     if (c->glm != 0 && c->glm != 1) return why = "glm must be 0 or 1", MHD_ERR_ARG;
     if ((c->flags & ~MHD_FLAG_ADJOINT) != 0) return why = "unknown flag bits", MHD_ERR_ARG;
     long long cells = 1;
@@ -366,6 +392,8 @@ mhd_status check_config(const mhd_config *c, std::string &why)
     if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return why = "cfl must be in (0, 1]", MHD_ERR_ARG;
     if (!(c->glm_alpha >= 0.0) || !std::isfinite(c->glm_alpha))
         return why = "glm_alpha must be >= 0", MHD_ERR_ARG;
+    if ((c->flags & MHD_FLAG_ADJOINT) && (c->limiter == MHD_WENOZ || c->time_order != 2))
+        return why = "the adjoint covers PLM with SSP-RK2 only", MHD_ERR_UNSUPPORTED;
     return MHD_OK;
 }
 
@@ -380,6 +408,7 @@ void free_ctx(mhd_ctx *ctx)
 {
     destroy_events(ctx);
     if (ctx->u1_scratch) (void)hipFree(ctx->u1_scratch);
+    if (ctx->u2_scratch) (void)hipFree(ctx->u2_scratch);
     if (ctx->part) (void)hipFree(ctx->part);
     if (ctx->result) (void)hipFree(ctx->result);
     if (ctx->flag) (void)hipFree(ctx->flag);
@@ -450,7 +479,8 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
     if (!out) return MHD_ERR_ARG;
     *out = nullptr;
     std::string why;
-    if (check_config(cfg, why) != MHD_OK) return MHD_ERR_ARG;
+    const mhd_status cst = check_config(cfg, why);
+    if (cst != MHD_OK) return cst;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MHD_ERR_NO_DEVICE;
     int dev = 0;
@@ -480,6 +510,8 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
     const Launch L = plan_stage(ctx, ty);
     ctx->part_cap = std::max(L.nblocks, CFL_MAX_BLOCKS);
     hipError_t e = hipMalloc(&ctx->u1_scratch, (size_t)NQ * ctx->ncell * ctx->elem);
+    if (e == hipSuccess && cfg->time_order == 3)
+        e = hipMalloc(&ctx->u2_scratch, (size_t)NQ * ctx->ncell * ctx->elem);
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->part, (size_t)NPART * ctx->part_cap * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->result, NPART * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->flag, sizeof(int));
@@ -597,9 +629,13 @@ mhd_status mhd_step_adjoint(mhd_ctx *ctx, const void *Un, const void *U1, const 
         return fail(ctx, MHD_ERR_ARG, "context was created without MHD_FLAG_ADJOINT");
     if ((const void *)lam_n == Un || (const void *)lam_n == U1)
         return fail(ctx, MHD_ERR_ARG, "lam_n must not alias a state buffer");
-    return with_scheme(ctx, [&](auto sch) {
+    return with_scheme(ctx, [&](auto sch) -> mhd_status {
         using S = decltype(sch);
-        return launch_adjoint_nd<typename S::T, S::SOLVER, S::LIM>(ctx, Un, U1, lam_next, lam_n, dt, c_h, damp);
+        if constexpr (S::LIM == LIM_WENOZ)
+            return fail(ctx, MHD_ERR_UNSUPPORTED, "no adjoint of WENO-Z");  // mhd_init refuses it first
+        else
+            return launch_adjoint_nd<typename S::T, S::SOLVER, S::LIM>(ctx, Un, U1, lam_next, lam_n, dt, c_h,
+                                                                      damp);
     });
 }
 

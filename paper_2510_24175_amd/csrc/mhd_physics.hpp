@@ -18,7 +18,8 @@ enum { NQ = 9 };
 enum { RHO = 0, VX = 1, VY = 2, VZ = 3, PRS = 4, BX = 5, BY = 6, BZ = 7, PSI = 8 };
 enum { MX = 1, MY = 2, MZ = 3, ENG = 4 };
 enum { SOLVER_HLL = 0, SOLVER_HLLD = 1 };
-enum { LIM_MINMOD = 0, LIM_MC = 1 };
+// reconstructions: PLM with the minmod or MC limiter, or fifth-order WENO-Z
+enum { LIM_MINMOD = 0, LIM_MC = 1, LIM_WENOZ = 2 };
 
 template <typename T> struct Num;
 
@@ -33,6 +34,7 @@ template <> struct Num<float> {
     static __device__ __forceinline__ float max(float a, float b) { return __builtin_fmaxf(a, b); }
     static __device__ __forceinline__ float copysign(float a, float b) { return __builtin_copysignf(a, b); }
     static constexpr float eps = 1.1920928955078125e-7f;
+    static constexpr float weno_eps = 1e-30f;  // normal, with a finite reciprocal
     static constexpr float big = 3.0e38f;
 };
 
@@ -45,6 +47,7 @@ template <> struct Num<double> {
     static __device__ __forceinline__ double max(double a, double b) { return __builtin_fmax(a, b); }
     static __device__ __forceinline__ double copysign(double a, double b) { return __builtin_copysign(a, b); }
     static constexpr double eps = 2.220446049250313e-16;
+    static constexpr double weno_eps = 1e-40;
     static constexpr double big = 1.0e300;
 };
 
@@ -92,6 +95,33 @@ template <int LIM, typename T> __device__ __forceinline__ T limited_slope(T a, T
     T m = Num<T>::min(Num<T>::abs(a), Num<T>::abs(b));
     if (LIM == LIM_MC) m = Num<T>::min(T(2) * m, T(0.5) * Num<T>::abs(a + b));
     return (a * b > T(0)) ? Num<T>::copysign(m, a) : T(0);
+}
+
+// WENO-Z value (Borges, Carmona, Costa & Don 2008; p = 1, eps = 1e-40 in
+// FP64, 1e-30 in FP32 where 1e-40 is subnormal and its reciprocal overflows) at
+// the right face of the middle of five cell values v0..v4: third-order
+// candidates, Jiang-Shu smoothness indicators, global indicator
+// tau5 = |beta0 - beta2|, weights d = (1, 6, 3)/10 scaled by
+// 1 + tau5 / (beta_k + eps).  The left face value of a cell is the same
+// function of the mirrored stencil.
+template <typename T> __device__ __forceinline__ T wenoz(T v0, T v1, T v2, T v3, T v4)
+{
+    const T q0 = (T(2) * v0 - T(7) * v1 + T(11) * v2) * T(1.0 / 6.0);
+    const T q1 = (-v1 + T(5) * v2 + T(2) * v3) * T(1.0 / 6.0);
+    const T q2 = (T(2) * v2 + T(5) * v3 - v4) * T(1.0 / 6.0);
+    const T e0 = v0 - T(2) * v1 + v2, f0 = v0 - T(4) * v1 + T(3) * v2;
+    const T e1 = v1 - T(2) * v2 + v3, f1 = v1 - v3;
+    const T e2 = v2 - T(2) * v3 + v4, f2 = T(3) * v2 - T(4) * v3 + v4;
+    const T c = T(13.0 / 12.0);
+    const T b0 = c * e0 * e0 + T(0.25) * f0 * f0;
+    const T b1 = c * e1 * e1 + T(0.25) * f1 * f1;
+    const T b2 = c * e2 * e2 + T(0.25) * f2 * f2;
+    const T tau = Num<T>::abs(b0 - b2);
+    const T eps = Num<T>::weno_eps;
+    const T a0 = T(0.1) * (T(1) + tau * Num<T>::rcp(b0 + eps));
+    const T a1 = T(0.6) * (T(1) + tau * Num<T>::rcp(b1 + eps));
+    const T a2 = T(0.3) * (T(1) + tau * Num<T>::rcp(b2 + eps));
+    return (a0 * q0 + a1 * q1 + a2 * q2) * Num<T>::rcp(a0 + a1 + a2);
 }
 
 // Fast magnetosonic speed from rho, p, |B|^2 and B_n^2:

@@ -107,24 +107,38 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Waves per SIMD the FP32 kernels are compiled for (register budget 168):
-// with 4-wave workgroups three of them share a compute unit.
-template <typename T> constexpr int stage_min_waves() { return sizeof(T) == 4 ? 3 : 1; }
-
-template <typename T, int SOLVER, int LIM, int NDIM, int STAGE, int TY>
-__global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(const StageArgs<T> a)
+// Waves per SIMD the FP32 kernels are compiled for: PLM, register budget
+// 168 (with 4-wave workgroups three of them share a compute unit); WENO-Z,
+// whose z window holds five planes, 256.
+template <typename T, int LIM> constexpr int stage_min_waves()
 {
+    return sizeof(T) == 4 ? (LIM == LIM_WENOZ ? 2 : 3) : 1;
+}
+
+// Stage kinds of the Runge-Kutta integrators (KIND): 1 U1 = Un + dt L(Un)
+// (first stage of both); 2 SSP-RK2 second and last stage
+// (Un + U1 + dt L(U1))/2; 3 SSP-RK3 second stage 3/4 Un + 1/4 (U1 + dt L(U1));
+// 4 SSP-RK3 last stage 1/3 Un + 2/3 (U2 + dt L(U2)).  The last stage damps
+// psi and reduces the CFL maxima and the conservation sums.
+constexpr bool last_stage(int kind) { return kind == 2 || kind == 4; }
+
+template <typename T, int SOLVER, int LIM, int NDIM, int KIND, int TY>
+__global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_kernel(const StageArgs<T> a)
+{
+    constexpr bool WENO = LIM == LIM_WENOZ;
+    constexpr bool LAST = last_stage(KIND);
+    constexpr int H = WENO ? 3 : 2;        // stencil half width (ghost layers)
     constexpr int NT = TX * TY;
-    constexpr int HY = NDIM >= 2 ? 2 : 0;  // y halo width in LDS
-    constexpr int PX = TX + 4;             // LDS row pitch
+    constexpr int HY = NDIM >= 2 ? H : 0;  // y halo width in LDS
+    constexpr int PX = TX + 2 * H;         // LDS row pitch
     constexpr int PY = TY + 2 * HY;        // LDS rows
     constexpr int PLANE = PX * PY;         // LDS elements per component
     constexpr int NFX = TY * (TX + 1);     // x-face items
     constexpr int NFY = NDIM >= 2 ? (TY + 1) * TX : 0;
     constexpr int NCHX = (NFX + TX - 1) / TX;       // 64-wide chunks of x items
     constexpr int NCHUNK = NCHX + NFY / TX;          // NFY is a multiple of TX
-    constexpr int NHX = 4 * TY;            // x-halo cells
-    constexpr int NH = NHX + (NDIM >= 2 ? 4 * TX : 0);
+    constexpr int NHX = 2 * H * TY;        // x-halo cells
+    constexpr int NH = NHX + (NDIM >= 2 ? 2 * H * TX : 0);
 
     __shared__ T P[NQ * PLANE];
     __shared__ T FXs[NQ * TY * (TX + 1)];
@@ -161,22 +175,22 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
         if (h < NH) {
             int lx, ly;
             if (h < NHX) {
-                const int r = h >> 2, s = h & 3;
-                lx = s < 2 ? s : TX + s;
+                const int r = h / (2 * H), s = h % (2 * H);
+                lx = s < H ? s : TX + s;
                 ly = r + HY;
             } else {
                 const int hy = h - NHX;
-                const int r4 = hy / TX, c = hy % TX;
-                lx = c + 2;
-                ly = r4 < 2 ? r4 : TY + r4;
+                const int rh = hy / TX, c = hy % TX;
+                lx = c + H;
+                ly = rh < H ? rh : TY + rh;
             }
             h_slot[m] = ly * PX + lx;
-            const int gi = remap_index(i0 + lx - 2, a.nx, a.per[0]);
+            const int gi = remap_index(i0 + lx - H, a.nx, a.per[0]);
             const int gj = remap_index(j0 + ly - HY, a.ny, a.per[1]);
             h_off[m] = (long long)gj * a.nx + gi;
         }
     }
-    const int own_slot = (ty + HY) * PX + tx + 2;
+    const int own_slot = (ty + HY) * PX + tx + H;
     bool ok = true;
 
     auto zoff = [&](int k) -> long long {
@@ -192,20 +206,28 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
         for (int q = 0; q < NQ; ++q) s[q] = limited_slope<LIM>(v0[q] - vm[q], vp[q] - v0[q]);
     };
 
-    // One face of the plane from the LDS stencil w0..w3 (stride apart):
-    // limited slopes of w1 and w2, face states, flux, store (dst may be null
-    // for padding items).
+    // One face of the plane from the LDS stencil w0..w(2H-1) (stride apart;
+    // the face lies between w(H-1) and wH): PLM, limited slopes of w1 and w2;
+    // WENO-Z, w0..w4 for the left state and w5..w1 for the right one.  Then
+    // the flux, stored (dst may be null for padding items).
     auto face_item = [&](auto dir, const T *base, int stride, T *dst, int fstride) {
         constexpr int D = decltype(dir)::value;
         T VL[NQ], VR[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const T *pq = base + q * PLANE;
-            const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride];
-            const T s1 = limited_slope<LIM>(w1 - w0, w2 - w1);
-            const T s2 = limited_slope<LIM>(w2 - w1, w3 - w2);
-            VL[q] = w1 + T(0.5) * s1;
-            VR[q] = w2 - T(0.5) * s2;
+            if constexpr (WENO) {
+                const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride],
+                        w4 = pq[4 * stride], w5 = pq[5 * stride];
+                VL[q] = wenoz(w0, w1, w2, w3, w4);
+                VR[q] = wenoz(w5, w4, w3, w2, w1);
+            } else {
+                const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride];
+                const T s1 = limited_slope<LIM>(w1 - w0, w2 - w1);
+                const T s2 = limited_slope<LIM>(w2 - w1, w3 - w2);
+                VL[q] = w1 + T(0.5) * s1;
+                VR[q] = w2 - T(0.5) * s2;
+            }
         }
         T F[NQ];
         face_flux<T, SOLVER>(VL, VR, D, a.ph, F);
@@ -215,24 +237,42 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
         }
     };
 
-    // z window
-    T V0[NQ], Vp1[NQ], D0[NQ], Fzm[NQ];
+    // z window.  PLM: V(k), V(k+1) and the limited slope of V(k).  WENO-Z:
+    // V(k-2) .. V(k+2).  Fzm is the flux through face k-1/2.
+    constexpr int ZW = WENO ? 5 : 2;
+    constexpr int ZC = WENO ? 2 : 0;       // window slot of plane k
+    T Wz[ZW][NQ], D0[NQ], Fzm[NQ];
     if (NDIM == 3) {
-        T Vm2[NQ], Vm1[NQ], Dm1[NQ], VL[NQ], VR[NQ];
-        prim_at(zoff(k0 - 2) + own, Vm2);
-        prim_at(zoff(k0 - 1) + own, Vm1);
-        prim_at(zoff(k0) + own, V0);
-        prim_at(zoff(k0 + 1) + own, Vp1);
-        slope9(Vm2, Vm1, V0, Dm1);
-        slope9(Vm1, V0, Vp1, D0);
+        T VL[NQ], VR[NQ];
+        if constexpr (WENO) {
+            // face k0-1/2: left state from planes k0-3 .. k0+1, right state
+            // from k0+2 .. k0-2
+            T Vm3[NQ];
+            prim_at(zoff(k0 - 3) + own, Vm3);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            VL[q] = Vm1[q] + T(0.5) * Dm1[q];
-            VR[q] = V0[q] - T(0.5) * D0[q];
+            for (int m = 0; m < 5; ++m) prim_at(zoff(k0 - 2 + m) + own, Wz[m]);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                VL[q] = wenoz(Vm3[q], Wz[0][q], Wz[1][q], Wz[2][q], Wz[3][q]);
+                VR[q] = wenoz(Wz[4][q], Wz[3][q], Wz[2][q], Wz[1][q], Wz[0][q]);
+            }
+        } else {
+            T Vm2[NQ], Vm1[NQ], Dm1[NQ];
+            prim_at(zoff(k0 - 2) + own, Vm2);
+            prim_at(zoff(k0 - 1) + own, Vm1);
+            prim_at(zoff(k0) + own, Wz[0]);
+            prim_at(zoff(k0 + 1) + own, Wz[1]);
+            slope9(Vm2, Vm1, Wz[0], Dm1);
+            slope9(Vm1, Wz[0], Wz[1], D0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                VL[q] = Vm1[q] + T(0.5) * Dm1[q];
+                VR[q] = Wz[0][q] - T(0.5) * D0[q];
+            }
         }
         face_flux<T, SOLVER>(VL, VR, 2, a.ph, Fzm);
     } else {
-        prim_at(own, V0);
+        prim_at(own, Wz[ZC]);
     }
 
     double smax = 0.0, cmax = 0.0;
@@ -244,7 +284,7 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
         const long long zk = zoff(k);
         // (a) primitives of plane k into LDS: own column and halo cell
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) P[q * PLANE + own_slot] = V0[q];
+        for (int q = 0; q < NQ; ++q) P[q * PLANE + own_slot] = Wz[ZC][q];
 #pragma unroll
         for (int m = 0; m < HPT; ++m) {
             if (t + m * NT < NH) {
@@ -257,21 +297,31 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
         // (b) z-face k+1/2 from the register window
         T Fzp[NQ], D1[NQ];
         if (NDIM == 3) {
-            T Vp2[NQ], VL[NQ], VR[NQ];
-            prim_at(zoff(k + 2) + own, Vp2);
-            slope9(V0, Vp1, Vp2, D1);
+            T Vn[NQ], VL[NQ], VR[NQ];
+            prim_at(zoff(k + ZW - ZC) + own, Vn);  // PLM: V(k+2); WENO-Z: V(k+3)
+            if constexpr (WENO) {
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                VL[q] = V0[q] + T(0.5) * D0[q];
-                VR[q] = Vp1[q] - T(0.5) * D1[q];
+                for (int q = 0; q < NQ; ++q) {
+                    VL[q] = wenoz(Wz[0][q], Wz[1][q], Wz[2][q], Wz[3][q], Wz[4][q]);
+                    VR[q] = wenoz(Vn[q], Wz[4][q], Wz[3][q], Wz[2][q], Wz[1][q]);
+                }
+            } else {
+                slope9(Wz[0], Wz[1], Vn, D1);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    VL[q] = Wz[0][q] + T(0.5) * D0[q];
+                    VR[q] = Wz[1][q] - T(0.5) * D1[q];
+                }
             }
             face_flux<T, SOLVER>(VL, VR, 2, a.ph, Fzp);
-            // slide the window: V(k+1), V(k+2) become V(k), V(k+1)
+            // slide the window by one plane
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                V0[q] = Vp1[q];
-                Vp1[q] = Vp2[q];
+            for (int m = 0; m + 1 < ZW; ++m) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) Wz[m][q] = Wz[m + 1][q];
             }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) Wz[ZW - 1][q] = Vn[q];
         }
         __syncthreads();
         // (c) x- and y-faces of the plane.  Items go out in 64-wide chunks,
@@ -284,14 +334,15 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
                 const bool valid = it < NFX;
                 const int r = valid ? it / (TX + 1) : 0;
                 const int f = valid ? it - r * (TX + 1) : 0;
-                // cells f-2 .. f+1 of row r
-                face_item(std::integral_constant<int, 0>{}, &P[(r + HY) * PX + f], 1, valid ? &FXs[r * (TX + 1) + f] : nullptr,
-                             TY * (TX + 1));
+                // cells f-H .. f+H-1 of row r
+                face_item(std::integral_constant<int, 0>{}, &P[(r + HY) * PX + f], 1,
+                          valid ? &FXs[r * (TX + 1) + f] : nullptr, TY * (TX + 1));
             } else {
                 const int it = (ch - NCHX) * TX + tx;
                 const int r = it / TX, c = it - r * TX;
-                // rows r-2 .. r+1 of column c
-                face_item(std::integral_constant<int, 1>{}, &P[r * PX + c + 2], PX, &FYs[r * TX + c], (TY + 1) * TX);
+                // rows r-H .. r+H-1 of column c
+                face_item(std::integral_constant<int, 1>{}, &P[r * PX + c + H], PX, &FYs[r * TX + c],
+                          (TY + 1) * TX);
             }
         }
         __syncthreads();
@@ -311,19 +362,28 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
                 L[q] = l;
             }
             T out[NQ];
-            if (STAGE == 1) {
+            if (KIND == 1) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) out[q] = a.uin[q * a.ncell + c] + a.dt * L[q];
-            } else {
+            } else if (KIND == 2) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
                     out[q] = T(0.5) * ((a.un[q * a.ncell + c] + a.uin[q * a.ncell + c]) + a.dt * L[q]);
-                out[PSI] *= a.damp;
+            } else if (KIND == 3) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    out[q] = T(0.75) * a.un[q * a.ncell + c] + T(0.25) * (a.uin[q * a.ncell + c] + a.dt * L[q]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    out[q] = a.un[q * a.ncell + c] * T(1.0 / 3.0) +
+                             T(2.0 / 3.0) * (a.uin[q * a.ncell + c] + a.dt * L[q]);
             }
+            if (LAST) out[PSI] *= a.damp;
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
                 __builtin_nontemporal_store(out[q], &a.uout[q * a.ncell + c]);  // not read again here
-            if (STAGE == 2) {
+            if (LAST) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) sum[q] += (double)out[q];
                 // FP64 signal speeds of every updated cell (a filter on an FP32
@@ -336,14 +396,14 @@ __global__ void __launch_bounds__(TX *TY, stage_min_waves<T>()) stage_kernel(con
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 Fzm[q] = Fzp[q];
-                D0[q] = D1[q];
+                if constexpr (!WENO) D0[q] = D1[q];
             }
         }
     }
 
     if (!ok) atomicOr(a.flag, 1);
 
-    if (STAGE == 2) {
+    if (LAST) {
         // block reduction of the partials in a fixed order
         __syncthreads();
         double *red = reinterpret_cast<double *>(P);  // LDS reuse, TY * NPART doubles

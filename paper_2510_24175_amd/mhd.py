@@ -23,12 +23,12 @@ MHD_ERR_UNSUPPORTED = -5
 
 MHD_F32, MHD_F64 = 0, 1
 MHD_HLL, MHD_HLLD = 0, 1
-MHD_MINMOD, MHD_MC = 0, 1
+MHD_MINMOD, MHD_MC, MHD_WENOZ = 0, 1, 2
 MHD_PERIODIC, MHD_OUTFLOW = 0, 1
 MHD_FLAG_ADJOINT = 1
 
 _RIEMANN = {"hll": MHD_HLL, "hlld": MHD_HLLD}
-_LIMITER = {"minmod": MHD_MINMOD, "mc": MHD_MC}
+_LIMITER = {"minmod": MHD_MINMOD, "mc": MHD_MC, "wenoz": MHD_WENOZ}
 _BC = {"periodic": MHD_PERIODIC, "outflow": MHD_OUTFLOW}
 _DTYPE = {"f32": MHD_F32, "f64": MHD_F64}
 TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64}
@@ -49,6 +49,8 @@ class mhd_config(ctypes.Structure):
         ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double),
         ("glm_alpha", ctypes.c_double),
+        ("time_order", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -111,6 +113,8 @@ def make_config(setup, dtype="f32", adjoint=False):
     c.gamma = float(setup["gamma"])
     c.cfl = float(setup["cfl"])
     c.glm_alpha = float(setup.get("glm_alpha", 0.1))
+    c.time_order = int(setup.get("time_order", 2))
+    c.reserved = 0
     return c
 
 
@@ -237,7 +241,9 @@ class Context:
         self._check(self.lib.mhd_timing_start(self.handle, int(capacity)), "mhd_timing_start")
 
     def timing_stop(self):
-        """(steps, stage1_ms, stage2_ms, reduce_ms) totals over the timed steps."""
+        """(steps, early_ms, last_ms, reduce_ms) totals over the timed steps:
+        the stage kernels before the last one (one with SSP-RK2, two with
+        SSP-RK3), the last stage kernel, the final reduction."""
         out = (ctypes.c_double * 4)()
         self._check(self.lib.mhd_timing_stop(self.handle, out), "mhd_timing_stop")
         return int(out[0]), out[1], out[2], out[3]

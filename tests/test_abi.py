@@ -49,11 +49,28 @@ def _base():
 @pytest.mark.parametrize("field,value", [
     ("ndim", 0), ("ndim", 4), ("dtype", 7), ("riemann", 3), ("limiter", 9), ("glm", 2),
     ("flags", 2), ("gamma", 1.0), ("cfl", 0.0), ("cfl", 1.5), ("glm_alpha", -0.1),
+    ("limiter", 3), ("time_order", 1), ("time_order", 4), ("reserved", 1),
 ])
 def test_invalid_config_is_rejected_before_device_use(field, value):
     cfg = _base()
     setattr(cfg, field, value)
     assert _init(cfg) == mhd.MHD_ERR_ARG
+
+
+def test_config_layout_matches_the_header():
+    # two int32 fields appended after the three doubles keep 8-byte alignment
+    # (sizes of the C struct on x86-64 / LP64)
+    assert ctypes.sizeof(mhd.mhd_config) == 152
+    assert mhd.mhd_config.time_order.offset == 144
+    assert mhd.mhd_config.reserved.offset == 148
+
+
+@pytest.mark.parametrize("limiter,time_order", [("wenoz", 2), ("wenoz", 3), ("minmod", 3)])
+def test_adjoint_of_weno_or_rk3_is_unsupported(limiter, time_order):
+    s, _ = W.turbulence(8)
+    s["limiter"], s["time_order"] = limiter, time_order
+    assert _init(mhd.make_config(s, "f32", adjoint=True)) == mhd.MHD_ERR_UNSUPPORTED
+    assert mhd.make_config(s, "f32").time_order == time_order
 
 
 def test_invalid_geometry_is_rejected():
