@@ -13,8 +13,10 @@ in HBM before timing starts.
 
 Prints one JSON line with the throughput (Mcell-updates/s), the roofline
 of the dominant kernel (stage 2) from HIP events recorded on the library's
-stream, FP64 figures on the same workload, and the FP64 CPU oracle timed on
-a bounded sample of the workload as a baseline.
+stream, FP64 figures on the same workload, the paper's benchmark scheme
+(WENO-Z + HLLD + GLM + SSP-RK3) on its per-GPU share (416^3) in FP64 and
+FP32, the adjoint/forward time ratio, and the FP64 CPU oracle timed on a
+bounded sample of the workload as a baseline.
 """
 import argparse
 import glob
@@ -54,13 +56,14 @@ def measured_counters(kernel_key):
     return ent
 
 
-def run_gpu(n, dtype, steps, warmup, quiet=False):
+def run_gpu(n, dtype, steps, warmup, limiter="minmod", time_order=2):
     import torch
 
     from paper_2510_24175_amd import workloads
     from paper_2510_24175_amd.mhd import Context
 
     setup, V = workloads.turbulence(n)
+    setup["limiter"], setup["time_order"] = limiter, time_order
     ctx = Context(setup, dtype)
     Vd = torch.from_numpy(V).cuda()
     del V
@@ -103,9 +106,11 @@ def run_gpu(n, dtype, steps, warmup, quiet=False):
         "ncell": ncell,
         "sums": sums,
     }
-    # algorithmic HBM traffic: stage 1 reads Un and writes U1 (18 s B/cell),
-    # stage 2 reads Un and U1 and writes U_next (27 s B/cell)
-    res["alg_bytes_step"] = 45 * s * ncell
+    # algorithmic HBM traffic: the first stage reads Un and writes U1
+    # (18 s B/cell), every later stage reads Un and its input stage and
+    # writes its output (27 s B/cell): 45 s B/cell per SSP-RK2 step, 72 s
+    # per SSP-RK3 step
+    res["alg_bytes_step"] = (18 + 27 * (time_order - 1)) * s * ncell
     res["alg_bytes_stage2"] = 27 * s * ncell
     res["hbm_frac_step"] = res["alg_bytes_step"] / (wall / steps) / (HBM_PEAK_GBS * 1e9)
     del a, b
@@ -195,6 +200,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-paper-scheme", action="store_true")
+    ap.add_argument("--paper-n", type=int, default=416)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -265,6 +272,29 @@ def main():
             "hbm_frac_step_algorithmic": round(r64["hbm_frac_step"], 4),
             "stage2_ms": round(r64["stage2_ms"], 4),
         }
+    if not args.no_paper_scheme:
+        # the scheme of the paper's benchmark runs (WENO-Z + HLLD + SSP-RK3,
+        # GLM in the strong-scaling runs, double precision) on its per-GPU
+        # share of the 832 x 832 x 416 strong-scaling grid split over one
+        # node's four GPUs (416^3), with the same turbulence fields
+        ps = {"workload": f"3D periodic decaying MHD turbulence {args.paper_n}^3, WENO-Z + HLLD + GLM, "
+                          "SSP-RK3, CFL 0.3"}
+        for dt_ in ("f64", "f32"):
+            r = run_gpu(args.paper_n, dt_, max(3, args.steps // 2), 2, limiter="wenoz", time_order=3)
+            ach = r["alg_bytes_stage2"] / (r["stage2_ms"] * 1e-3) / 1e9
+            ps[dt_] = {"value": round(r["mcells"], 2), "unit": "Mcell-updates/s",
+                       "ms_per_step": round(r["ms_per_step"], 4),
+                       "hbm_frac_step_algorithmic": round(r["hbm_frac_step"], 4),
+                       "stage_ms": {"first_two": round(r["stage1_ms"], 4), "last": round(r["stage2_ms"], 4),
+                                    "final_reduce": round(r["reduce_ms"], 4)},
+                       "last_stage_gbs": round(ach, 1)}
+            cnt = measured_counters(f"stage3_turbulence{args.paper_n}_{dt_}_wenoz_rk3")
+            if cnt and cnt.get("valu_wave_insts"):
+                ps[dt_]["last_stage_valu_issue_frac"] = round(
+                    cnt["valu_wave_insts"] * 4 / (1024 * 2.4e9 * r["stage2_ms"] * 1e-3), 4)
+            print(f"# paper scheme {dt_} {args.paper_n}^3: {r['ms_per_step']:.3f} ms/step", file=sys.stderr,
+                  flush=True)
+        out["paper_scheme"] = ps
     if not args.no_adjoint:
         # adjoint/forward time ratio at the adjoint workload (128^3 FP32)
         # and at the benchmark grid
