@@ -14,9 +14,10 @@ in HBM before timing starts.
 Prints one JSON line with the throughput (Mcell-updates/s), the roofline
 of the dominant kernel (stage 2) from HIP events recorded on the library's
 stream, FP64 figures on the same workload, the paper's benchmark scheme
-(WENO-Z + HLLD + GLM + SSP-RK3) on its per-GPU share (416^3) in FP64 and
-FP32, the adjoint/forward time ratio, and the FP64 CPU oracle timed on a
-bounded sample of the workload as a baseline.
+(WENO-Z + HLLD + GLM + SSP-RK3) on its two problems (3D Orszag-Tang, 3D
+circularly polarised Alfven wave) at the per-GPU share 416^3, the
+adjoint/forward time ratio, and the FP64 CPU oracle timed on a bounded
+sample of the workload as a baseline.
 """
 import argparse
 import glob
@@ -56,13 +57,13 @@ def measured_counters(kernel_key):
     return ent
 
 
-def run_gpu(n, dtype, steps, warmup, limiter="minmod", time_order=2):
+def run_gpu(n, dtype, steps, warmup, workload="turbulence", limiter="minmod", time_order=2):
     import torch
 
     from paper_2510_24175_amd import workloads
     from paper_2510_24175_amd.mhd import Context
 
-    setup, V = workloads.turbulence(n)
+    setup, V = getattr(workloads, workload)(n)
     setup["limiter"], setup["time_order"] = limiter, time_order
     ctx = Context(setup, dtype)
     Vd = torch.from_numpy(V).cuda()
@@ -202,6 +203,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-paper-scheme", action="store_true")
     ap.add_argument("--paper-n", type=int, default=416)
+    ap.add_argument("--paper-cases", default="ot3d_f64,ot3d_f32,cpa3d_f64",
+                    help="comma list of paper-scheme runs (ot3d_f64, ot3d_f32, cpa3d_f64, cpa3d_f32)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -274,26 +277,31 @@ def main():
         }
     if not args.no_paper_scheme:
         # the scheme of the paper's benchmark runs (WENO-Z + HLLD + SSP-RK3,
-        # GLM in the strong-scaling runs, double precision) on its per-GPU
+        # GLM in the strong-scaling runs, double precision) on the per-GPU
         # share of the 832 x 832 x 416 strong-scaling grid split over one
-        # node's four GPUs (416^3), with the same turbulence fields
-        ps = {"workload": f"3D periodic decaying MHD turbulence {args.paper_n}^3, WENO-Z + HLLD + GLM, "
-                          "SSP-RK3, CFL 0.3"}
-        for dt_ in ("f64", "f32"):
-            r = run_gpu(args.paper_n, dt_, max(3, args.steps // 2), 2, limiter="wenoz", time_order=3)
+        # node's four GPUs (416^3), for the paper's two problems: the 3D
+        # Orszag-Tang vortex (FP64 and FP32) and the 3D circularly polarised
+        # Alfven wave (FP64)
+        pn = args.paper_n
+        ps = {"workload": f"3D Orszag-Tang vortex and 3D circularly polarised Alfven wave, {pn}^3, "
+                          "WENO-Z + HLLD + GLM, SSP-RK3, CFL 0.3", "n": [pn] * 3}
+        cases = [c.strip() for c in args.paper_cases.split(",") if c.strip()]
+        for key in cases:
+            wl = {"ot3d": "orszag_tang_3d", "cpa3d": "cpa_wave_3d"}[key.split("_")[0]]
+            dt_ = key.split("_")[1]
+            r = run_gpu(pn, dt_, max(3, args.steps // 2), 2, workload=wl, limiter="wenoz", time_order=3)
             ach = r["alg_bytes_stage2"] / (r["stage2_ms"] * 1e-3) / 1e9
-            ps[dt_] = {"value": round(r["mcells"], 2), "unit": "Mcell-updates/s",
+            ps[key] = {"value": round(r["mcells"], 2), "unit": "Mcell-updates/s",
                        "ms_per_step": round(r["ms_per_step"], 4),
                        "hbm_frac_step_algorithmic": round(r["hbm_frac_step"], 4),
                        "stage_ms": {"first_two": round(r["stage1_ms"], 4), "last": round(r["stage2_ms"], 4),
                                     "final_reduce": round(r["reduce_ms"], 4)},
                        "last_stage_gbs": round(ach, 1)}
-            cnt = measured_counters(f"stage3_turbulence{args.paper_n}_{dt_}_wenoz_rk3")
+            cnt = measured_counters(f"stage3_{wl}{pn}_{dt_}_wenoz_rk3")
             if cnt and cnt.get("valu_wave_insts"):
-                ps[dt_]["last_stage_valu_issue_frac"] = round(
+                ps[key]["last_stage_valu_issue_frac"] = round(
                     cnt["valu_wave_insts"] * 4 / (1024 * 2.4e9 * r["stage2_ms"] * 1e-3), 4)
-            print(f"# paper scheme {dt_} {args.paper_n}^3: {r['ms_per_step']:.3f} ms/step", file=sys.stderr,
-                  flush=True)
+            print(f"# paper scheme {key} {pn}^3: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         out["paper_scheme"] = ps
     if not args.no_adjoint:
         # adjoint/forward time ratio at the adjoint workload (128^3 FP32)

@@ -18,8 +18,12 @@ of those runs are not printed, so these are synthetic stand-ins):
 * ``turbulence``   3D periodic decaying turbulence, seeded Gaussian mode
                    sums with k^-2 power in 1 <= |k| <= 4, divergence-free B.
 * ``orszag_tang``  2D periodic vortex with seeded +-5% amplitudes.
+* ``orszag_tang_3d`` 3D periodic vortex: the 2D fields with a z-modulated
+                   velocity (the paper's first benchmark problem).
 * ``cpa_wave``     circularly polarised Alfven wave (exact nonlinear
-                   travelling solution), 1D/2D/3D, any direction.
+                   travelling solution), 1D/2D/3D, any direction;
+                   ``cpa_wave_3d`` along the cube diagonal (the paper's
+                   second benchmark problem).
 * ``sod``, ``uniform``, ``stationary_contact``: closed-form test states.
 """
 import math
@@ -150,6 +154,21 @@ def cpa_wave(n, ndim=1, k=(1, 0, 0), amplitude=1e-3, rho=1.0, p=1.0, b0=1.0, rie
     return s, V
 
 
+def cpa_wave_3d(n, amplitude=0.1, riemann="hlld", cfl=0.3, limiter="wenoz", time_order=3):
+    """3D circularly polarised Alfven wave on the periodic unit cube with
+    k = (1, 1, 1) (wavelength 1/sqrt 3 along the diagonal), in the usual
+    parameters of the test (Toth 2000; Gardiner & Stone 2008): rho = 1,
+    p = 0.1, B_parallel = 1, perpendicular amplitude 0.1, gamma = 5/3.  The
+    scheme defaults to the paper's benchmark one (WENO-Z, SSP-RK3)."""
+    if isinstance(n, int):
+        n = (n, n, n)
+    s, V = cpa_wave(n, ndim=3, k=(1, 1, 1), amplitude=amplitude, rho=1.0, p=0.1, b0=1.0,
+                    riemann=riemann, cfl=cfl)
+    s["name"] = "cpa3d"
+    s["limiter"], s["time_order"] = limiter, time_order
+    return s, V
+
+
 # -------------------------------------------------------- turbulence -------
 
 def half_space_modes(kmax=4):
@@ -276,4 +295,35 @@ def orszag_tang(n=1024, seed=3, riemann="hlld", cfl=0.3, t_end=0.5):
     V[5, 0] = -b0 * a[2] * np.sin(2 * math.pi * Y)
     V[6, 0] = b0 * a[3] * np.sin(4 * math.pi * X)
     s["amplitudes"] = a.tolist()
+    return s, V
+
+
+def orszag_tang_3d(n, eps=0.2, riemann="hlld", cfl=0.3, limiter="wenoz", time_order=3, t_end=None):
+    """3D periodic Orszag-Tang-type vortex on [0,1]^3: the 2D vortex
+    (rho = 25/(36 pi), p = 5/(12 pi), gamma = 5/3, B = B0 (-sin 2pi y,
+    sin 4pi x, 0), B0 = 1/sqrt(4 pi)) with the velocity modulated along z,
+    v = ((1 + eps sin 2pi z)(-sin 2pi y), (1 + eps sin 2pi z) sin 2pi x,
+    eps sin 2pi z), eps = 0.2, the way Helzel, Rossmanith & Taetz (2011)
+    extend the vortex to three dimensions.  B is solenoidal and the fields
+    are symmetric under a half turn about the z axis through the box
+    centre.  The scheme defaults to the paper's benchmark one (WENO-Z,
+    SSP-RK3)."""
+    if isinstance(n, int):
+        n = (n, n, n)
+    s = make_setup("orszag_tang_3d", 3, n, gamma=5.0 / 3.0, cfl=cfl, riemann=riemann,
+                   limiter=limiter, time_order=time_order, t_end=t_end)
+    x, y, z = cell_centres(s)
+    sx, sy = np.sin(2 * math.pi * x), np.sin(2 * math.pi * y)
+    s4x = np.sin(4 * math.pi * x)
+    mz = 1.0 + eps * np.sin(2 * math.pi * z)
+    b0 = 1.0 / math.sqrt(4 * math.pi)
+    V = _empty(s)
+    V[0] = 25.0 / (36.0 * math.pi)
+    V[1] = -mz[:, None, None] * sy[None, :, None]
+    V[2] = mz[:, None, None] * sx[None, None, :]
+    V[3] = (eps * np.sin(2 * math.pi * z))[:, None, None]
+    V[4] = 5.0 / (12.0 * math.pi)
+    V[5] = -b0 * sy[None, :, None]
+    V[6] = b0 * s4x[None, None, :]
+    s["eps"] = float(eps)
     return s, V

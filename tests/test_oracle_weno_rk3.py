@@ -229,3 +229,46 @@ def test_alfven_wave_third_order():
     Vf = o.cons_to_prim(U)
     e_plm = np.mean(np.abs(Vf[[1, 2, 3, 5, 6, 7]] - V[[1, 2, 3, 5, 6, 7]]))
     assert e[2] <= 0.1 * e_plm, (e[2], e_plm)
+
+
+def test_orszag_tang_3d_half_turn_symmetry():
+    # the 3D vortex is symmetric under a half turn about the z axis through
+    # the box centre, (x, y) -> (1 - x, 1 - y): scalars and z components keep
+    # their values, x and y components change sign
+    s, V = W.orszag_tang_3d((24, 24, 12))
+    o = C.Oracle(s)
+    U, _, _ = o.run(o.prim_to_cons(V), nsteps=20)
+    R = U[:, :, ::-1, ::-1].copy()
+    for q in (1, 2, 5, 6):
+        R[q] *= -1
+    scale = np.abs(U).max(axis=(1, 2, 3), keepdims=True) + 1e-300
+    assert (np.abs(U - R) / scale)[:8].max() <= 1e-12
+
+
+def test_orszag_tang_3d_initial_fields():
+    # solenoidal B (each component is independent of its own coordinate),
+    # the z-modulated velocity, the 2D vortex's thermodynamic state
+    s, V = W.orszag_tang_3d((16, 12, 8))
+    assert np.ptp(V[5], axis=2).max() == 0.0 and np.ptp(V[6], axis=1).max() == 0.0
+    assert np.all(V[7] == 0.0)
+    x, y, z = W.cell_centres(s)
+    mz = 1 + 0.2 * np.sin(2 * math.pi * z)
+    np.testing.assert_allclose(V[1, :, 3, 5], -mz * math.sin(2 * math.pi * y[3]), rtol=1e-15)
+    np.testing.assert_allclose(V[3, :, 0, 0], 0.2 * np.sin(2 * math.pi * z), rtol=1e-15)
+    assert V[0, 0, 0, 0] == 25 / (36 * math.pi) and V[4, 0, 0, 0] == 5 / (12 * math.pi)
+
+
+def test_cpa_3d_diagonal_third_order():
+    # the diagonal wave crosses all three axes, so every direction's
+    # reconstruction and flux enter the error; one period, 16^3 and 32^3
+    def err(n):
+        s, V = W.cpa_wave_3d(n)
+        o = C.Oracle(s)
+        U, _, _ = o.run(o.prim_to_cons(V), t_end=s["period"])
+        Vf = o.cons_to_prim(U)
+        comps = [1, 2, 3, 5, 6, 7]
+        return np.mean(np.abs(Vf[comps] - V[comps]))
+
+    e16, e32 = err(16), err(32)
+    assert math.log2(e16 / e32) >= 2.7, (e16, e32)
+    assert e32 <= 2e-5, e32
