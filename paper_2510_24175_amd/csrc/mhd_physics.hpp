@@ -97,31 +97,46 @@ template <int LIM, typename T> __device__ __forceinline__ T limited_slope(T a, T
     return (a * b > T(0)) ? Num<T>::copysign(m, a) : T(0);
 }
 
-// WENO-Z value (Borges, Carmona, Costa & Don 2008; p = 1, eps = 1e-40 in
-// FP64, 1e-30 in FP32 where 1e-40 is subnormal and its reciprocal overflows) at
-// the right face of the middle of five cell values v0..v4: third-order
-// candidates, Jiang-Shu smoothness indicators, global indicator
-// tau5 = |beta0 - beta2|, weights d = (1, 6, 3)/10 scaled by
-// 1 + tau5 / (beta_k + eps).  The left face value of a cell is the same
-// function of the mirrored stencil.
-template <typename T> __device__ __forceinline__ T wenoz(T v0, T v1, T v2, T v3, T v4)
+// WENO-Z face values of one cell (Borges, Carmona, Costa & Don 2008; p = 1,
+// eps = 1e-40 in FP64, 1e-30 in FP32 where 1e-40 is subnormal and its
+// reciprocal overflows) from the five cell values v0..v4 centred on it: the
+// value at its right face (rgt, x_{i+1/2}) and at its left face (lft,
+// x_{i-1/2}).  The three candidate quadratics are fitted to the cell sets
+// S0 = {v0,v1,v2}, S1 = {v1,v2,v3}, S2 = {v2,v3,v4}; written around v2 with
+// e_k their second differences and G_k half their one-sided first
+// differences (G0 = (v0 - 4v1 + 3v2)/2, G1 = (v1 - v3)/2,
+// G2 = (3v2 - 4v3 + v4)/2), a candidate's face values are
+// v2 + e_k/12 -+ G_k/2 and its Jiang-Shu smoothness indicator is
+// beta_k = 13/12 e_k^2 + G_k^2.  Both faces share beta_k and the global
+// indicator tau5 = |beta0 - beta2|; their linear weights are mirror images,
+// (1, 6, 3)/10 on (S0, S1, S2) for the right face and (3, 6, 1)/10 for the
+// left, each scaled by 1 + tau5 / (beta_k + eps).
+template <typename T>
+__device__ __forceinline__ void wenoz_pair(T v0, T v1, T v2, T v3, T v4, T &rgt, T &lft)
 {
-    const T q0 = (T(2) * v0 - T(7) * v1 + T(11) * v2) * T(1.0 / 6.0);
-    const T q1 = (-v1 + T(5) * v2 + T(2) * v3) * T(1.0 / 6.0);
-    const T q2 = (T(2) * v2 + T(5) * v3 - v4) * T(1.0 / 6.0);
-    const T e0 = v0 - T(2) * v1 + v2, f0 = v0 - T(4) * v1 + T(3) * v2;
-    const T e1 = v1 - T(2) * v2 + v3, f1 = v1 - v3;
-    const T e2 = v2 - T(2) * v3 + v4, f2 = T(3) * v2 - T(4) * v3 + v4;
+    const T e0 = (v0 + v2) - T(2) * v1, e1 = (v1 + v3) - T(2) * v2, e2 = (v2 + v4) - T(2) * v3;
+    const T G0 = T(0.5) * v0 - T(2) * v1 + T(1.5) * v2;
+    const T G1 = T(0.5) * (v1 - v3);
+    const T G2 = T(1.5) * v2 - T(2) * v3 + T(0.5) * v4;
     const T c = T(13.0 / 12.0);
-    const T b0 = c * e0 * e0 + T(0.25) * f0 * f0;
-    const T b1 = c * e1 * e1 + T(0.25) * f1 * f1;
-    const T b2 = c * e2 * e2 + T(0.25) * f2 * f2;
+    const T b0 = c * e0 * e0 + G0 * G0;
+    const T b1 = c * e1 * e1 + G1 * G1;
+    const T b2 = c * e2 * e2 + G2 * G2;
     const T tau = Num<T>::abs(b0 - b2);
     const T eps = Num<T>::weno_eps;
-    const T a0 = T(0.1) * (T(1) + tau * Num<T>::rcp(b0 + eps));
-    const T a1 = T(0.6) * (T(1) + tau * Num<T>::rcp(b1 + eps));
-    const T a2 = T(0.3) * (T(1) + tau * Num<T>::rcp(b2 + eps));
-    return (a0 * q0 + a1 * q1 + a2 * q2) * Num<T>::rcp(a0 + a1 + a2);
+    const T r0 = tau * Num<T>::rcp(b0 + eps);
+    const T r1 = tau * Num<T>::rcp(b1 + eps);
+    const T r2 = tau * Num<T>::rcp(b2 + eps);
+    // candidate deviations from v2 at the two faces
+    const T h0 = e0 * T(1.0 / 12.0), h1 = e1 * T(1.0 / 12.0), h2 = e2 * T(1.0 / 12.0);
+    const T d0r = h0 + T(0.5) * G0, d0l = h0 - T(0.5) * G0;
+    const T d1r = h1 - T(0.5) * G1, d1l = h1 + T(0.5) * G1;
+    const T d2r = h2 - T(0.5) * G2, d2l = h2 + T(0.5) * G2;
+    const T a1 = T(0.6) + T(0.6) * r1;
+    const T a0r = T(0.1) + T(0.1) * r0, a2r = T(0.3) + T(0.3) * r2;
+    const T a0l = T(0.3) + T(0.3) * r0, a2l = T(0.1) + T(0.1) * r2;
+    rgt = v2 + (a0r * d0r + a1 * d1r + a2r * d2r) * Num<T>::rcp(a0r + a1 + a2r);
+    lft = v2 + (a0l * d0l + a1 * d1l + a2l * d2l) * Num<T>::rcp(a0l + a1 + a2l);
 }
 
 // Fast magnetosonic speed from rho, p, |B|^2 and B_n^2:

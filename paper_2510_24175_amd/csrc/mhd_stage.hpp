@@ -109,7 +109,7 @@ __device__ __forceinline__ double wave_max(double v)
 
 // Waves per SIMD the FP32 kernels are compiled for: PLM, register budget
 // 168 (with 4-wave workgroups three of them share a compute unit); WENO-Z,
-// whose z window holds five planes, 256.
+// whose workgroups hold twice the LDS (two per compute unit), 256.
 template <typename T, int LIM> constexpr int stage_min_waves()
 {
     return sizeof(T) == 4 ? (LIM == LIM_WENOZ ? 2 : 3) : 1;
@@ -139,10 +139,33 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
     constexpr int NCHUNK = NCHX + NFY / TX;          // NFY is a multiple of TX
     constexpr int NHX = 2 * H * TY;        // x-halo cells
     constexpr int NH = NHX + (NDIM >= 2 ? 2 * H * TX : 0);
+    // WENO-Z reconstructs every cell once per direction (both of its face
+    // values) before the face fluxes: x for cells -1 .. TX of each row, y for
+    // rows -1 .. TY of each column; the values go to LDS edge arrays
+    // E[2][NQ][rows][cells] (right/upper face first).
+    constexpr int NXE = TX + 2;                          // cells per row with an x edge
+    constexpr int NYE = TY + 2;                          // rows with a y edge
+    constexpr int NRX = WENO ? TY * NXE : 0;             // x reconstruction items
+    constexpr int NRY = (WENO && NDIM >= 2) ? NYE * TX : 0;
+    constexpr int NRCH = (NRX + NRY + TX - 1) / TX;      // their 64-wide chunks
+    // LDS: PLM [P][FX][FY]; WENO-Z [P, with FX FY over it once P is used][EX][EY]
+    constexpr int SZP = NQ * PLANE;
+    constexpr int SZFX = NQ * TY * (TX + 1);
+    constexpr int SZFY = NDIM >= 2 ? NQ * (TY + 1) * TX : 0;
+    constexpr int SZEX = 2 * NQ * TY * NXE;
+    constexpr int SZEY = 2 * NQ * NYE * TX;
+    constexpr int OFX = WENO ? 0 : SZP;
+    constexpr int OFY = OFX + SZFX;
+    constexpr int OEX = WENO ? (SZP > SZFX + SZFY ? SZP : SZFX + SZFY) : OFY + SZFY;
+    constexpr int OEY = OEX + (WENO ? SZEX : 0);
+    constexpr int SZL = OEY + ((WENO && NDIM >= 2) ? SZEY : 0);
 
-    __shared__ T P[NQ * PLANE];
-    __shared__ T FXs[NQ * TY * (TX + 1)];
-    __shared__ T FYs[NDIM >= 2 ? NQ * (TY + 1) * TX : 1];
+    __shared__ T lds[SZL];
+    T *const P = lds;
+    T *const FXs = lds + OFX;
+    T *const FYs = lds + OFY;
+    T *const EX = lds + OEX;
+    T *const EY = lds + OEY;
 
     const int t = threadIdx.x;
     const int tx = t & (TX - 1);
@@ -206,29 +229,10 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
         for (int q = 0; q < NQ; ++q) s[q] = limited_slope<LIM>(v0[q] - vm[q], vp[q] - v0[q]);
     };
 
-    // One face of the plane from the LDS stencil w0..w(2H-1) (stride apart;
-    // the face lies between w(H-1) and wH): PLM, limited slopes of w1 and w2;
-    // WENO-Z, w0..w4 for the left state and w5..w1 for the right one.  Then
-    // the flux, stored (dst may be null for padding items).
-    auto face_item = [&](auto dir, const T *base, int stride, T *dst, int fstride) {
+    // Flux through one face of the plane from its two states, stored (dst
+    // may be null for padding items).
+    auto flux_item = [&](auto dir, const T *VL, const T *VR, T *dst, int fstride) {
         constexpr int D = decltype(dir)::value;
-        T VL[NQ], VR[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const T *pq = base + q * PLANE;
-            if constexpr (WENO) {
-                const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride],
-                        w4 = pq[4 * stride], w5 = pq[5 * stride];
-                VL[q] = wenoz(w0, w1, w2, w3, w4);
-                VR[q] = wenoz(w5, w4, w3, w2, w1);
-            } else {
-                const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride];
-                const T s1 = limited_slope<LIM>(w1 - w0, w2 - w1);
-                const T s2 = limited_slope<LIM>(w2 - w1, w3 - w2);
-                VL[q] = w1 + T(0.5) * s1;
-                VR[q] = w2 - T(0.5) * s2;
-            }
-        }
         T F[NQ];
         face_flux<T, SOLVER>(VL, VR, D, a.ph, F);
         if (dst) {
@@ -236,25 +240,43 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             for (int q = 0; q < NQ; ++q) dst[q * fstride] = F[q];
         }
     };
+    // PLM face from the LDS stencil w0..w3 (stride apart; the face lies
+    // between w1 and w2): limited slopes of w1 and w2, face states, flux.
+    auto face_item = [&](auto dir, const T *base, int stride, T *dst, int fstride) {
+        T VL[NQ], VR[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const T *pq = base + q * PLANE;
+            const T w0 = pq[0], w1 = pq[stride], w2 = pq[2 * stride], w3 = pq[3 * stride];
+            const T s1 = limited_slope<LIM>(w1 - w0, w2 - w1);
+            const T s2 = limited_slope<LIM>(w2 - w1, w3 - w2);
+            VL[q] = w1 + T(0.5) * s1;
+            VR[q] = w2 - T(0.5) * s2;
+        }
+        flux_item(dir, VL, VR, dst, fstride);
+    };
 
     // z window.  PLM: V(k), V(k+1) and the limited slope of V(k).  WENO-Z:
-    // V(k-2) .. V(k+2).  Fzm is the flux through face k-1/2.
-    constexpr int ZW = WENO ? 5 : 2;
-    constexpr int ZC = WENO ? 2 : 0;       // window slot of plane k
-    T Wz[ZW][NQ], D0[NQ], Fzm[NQ];
+    // V(k-1) .. V(k+2) and ZT, the upper face value of cell k.  Fzm is the
+    // flux through face k-1/2.
+    constexpr int ZW = WENO ? 4 : 2;
+    constexpr int ZC = WENO ? 1 : 0;       // window slot of plane k
+    T Wz[ZW][NQ], D0[NQ], ZT[NQ], Fzm[NQ];
     if (NDIM == 3) {
         T VL[NQ], VR[NQ];
         if constexpr (WENO) {
-            // face k0-1/2: left state from planes k0-3 .. k0+1, right state
-            // from k0+2 .. k0-2
-            T Vm3[NQ];
+            // cell k0-1 gives the lower state of face k0-1/2, cell k0 the
+            // upper one and its own upper face value
+            T Vm3[NQ], Vm2[NQ];
             prim_at(zoff(k0 - 3) + own, Vm3);
+            prim_at(zoff(k0 - 2) + own, Vm2);
 #pragma unroll
-            for (int m = 0; m < 5; ++m) prim_at(zoff(k0 - 2 + m) + own, Wz[m]);
+            for (int m = 0; m < 4; ++m) prim_at(zoff(k0 - 1 + m) + own, Wz[m]);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                VL[q] = wenoz(Vm3[q], Wz[0][q], Wz[1][q], Wz[2][q], Wz[3][q]);
-                VR[q] = wenoz(Wz[4][q], Wz[3][q], Wz[2][q], Wz[1][q], Wz[0][q]);
+                T lo;
+                wenoz_pair(Vm3[q], Vm2[q], Wz[0][q], Wz[1][q], Wz[2][q], VL[q], lo);
+                wenoz_pair(Vm2[q], Wz[0][q], Wz[1][q], Wz[2][q], Wz[3][q], ZT[q], VR[q]);
             }
         } else {
             T Vm2[NQ], Vm1[NQ], Dm1[NQ];
@@ -282,6 +304,8 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
 
     for (int k = k0; k < k1; ++k) {
         const long long zk = zoff(k);
+        // WENO-Z: the fluxes of the previous plane sit where P goes
+        if (WENO && k > k0) __syncthreads();
         // (a) primitives of plane k into LDS: own column and halo cell
 #pragma unroll
         for (int q = 0; q < NQ; ++q) P[q * PLANE + own_slot] = Wz[ZC][q];
@@ -300,10 +324,12 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             T Vn[NQ], VL[NQ], VR[NQ];
             prim_at(zoff(k + ZW - ZC) + own, Vn);  // PLM: V(k+2); WENO-Z: V(k+3)
             if constexpr (WENO) {
+                // cell k+1: its lower face value closes face k+1/2, its upper
+                // one is carried to the next plane
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    VL[q] = wenoz(Wz[0][q], Wz[1][q], Wz[2][q], Wz[3][q], Wz[4][q]);
-                    VR[q] = wenoz(Vn[q], Wz[4][q], Wz[3][q], Wz[2][q], Wz[1][q]);
+                    VL[q] = ZT[q];
+                    wenoz_pair(Wz[0][q], Wz[1][q], Wz[2][q], Wz[3][q], Vn[q], ZT[q], VR[q]);
                 }
             } else {
                 slope9(Wz[0], Wz[1], Vn, D1);
@@ -324,25 +350,95 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             for (int q = 0; q < NQ; ++q) Wz[ZW - 1][q] = Vn[q];
         }
         __syncthreads();
-        // (c) x- and y-faces of the plane.  Items go out in 64-wide chunks,
-        // one chunk per wave at a time; x items are padded to whole chunks so
-        // every chunk is a single direction and the solver is inlined with a
-        // compile-time frame.
-        for (int ch = wave; ch < NCHUNK; ch += TY) {
-            if (ch < NCHX) {
+        if constexpr (WENO) {
+            // (c0) WENO-Z face values of every cell the plane's faces need,
+            // each from the five cells centred on it: x items for cells
+            // -1 .. TX of each row, y items for rows -1 .. TY of each column.
+            // Direction only changes addresses, so chunks mix the two.
+            for (int ch = wave; ch < NRCH; ch += TY) {
                 const int it = ch * TX + tx;
-                const bool valid = it < NFX;
-                const int r = valid ? it / (TX + 1) : 0;
-                const int f = valid ? it - r * (TX + 1) : 0;
-                // cells f-H .. f+H-1 of row r
-                face_item(std::integral_constant<int, 0>{}, &P[(r + HY) * PX + f], 1,
-                          valid ? &FXs[r * (TX + 1) + f] : nullptr, TY * (TX + 1));
-            } else {
-                const int it = (ch - NCHX) * TX + tx;
-                const int r = it / TX, c = it - r * TX;
-                // rows r-H .. r+H-1 of column c
-                face_item(std::integral_constant<int, 1>{}, &P[r * PX + c + H], PX, &FYs[r * TX + c],
-                          (TY + 1) * TX);
+                if (it < NRX + NRY) {
+                    const T *src;
+                    int stride;
+                    T *dst;
+                    int esize;
+                    if (it < NRX) {
+                        const int r = it / NXE, c = it - r * NXE;
+                        src = &P[(r + HY) * PX + c];
+                        stride = 1;
+                        dst = &EX[r * NXE + c];
+                        esize = NQ * TY * NXE;
+                    } else {
+                        const int iy = it - NRX;
+                        const int r = iy / TX, c = iy - r * TX;
+                        src = &P[r * PX + c + H];
+                        stride = PX;
+                        dst = &EY[r * TX + c];
+                        esize = NQ * NYE * TX;
+                    }
+                    const int qs = esize / NQ;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        const T *pq = src + q * PLANE;
+                        T hi, lo;
+                        wenoz_pair(pq[0], pq[stride], pq[2 * stride], pq[3 * stride], pq[4 * stride], hi, lo);
+                        dst[q * qs] = hi;
+                        dst[esize + q * qs] = lo;
+                    }
+                }
+            }
+            __syncthreads();
+            // (c1) face fluxes from the edge values: x face f of row r between
+            // cells f-1 and f, y face r of column c between rows r-1 and r;
+            // the fluxes overwrite P
+            for (int ch = wave; ch < NCHUNK; ch += TY) {
+                T VL[NQ], VR[NQ];
+                if (ch < NCHX) {
+                    const int it = ch * TX + tx;
+                    const bool valid = it < NFX;
+                    const int r = valid ? it / (TX + 1) : 0;
+                    const int f = valid ? it - r * (TX + 1) : 0;
+                    constexpr int QS = TY * NXE;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        VL[q] = EX[q * QS + r * NXE + f];
+                        VR[q] = EX[NQ * QS + q * QS + r * NXE + f + 1];
+                    }
+                    flux_item(std::integral_constant<int, 0>{}, VL, VR,
+                              valid ? &FXs[r * (TX + 1) + f] : nullptr, TY * (TX + 1));
+                } else {
+                    const int it = (ch - NCHX) * TX + tx;
+                    const int r = it / TX, c = it - r * TX;
+                    constexpr int QS = NYE * TX;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        VL[q] = EY[q * QS + r * TX + c];
+                        VR[q] = EY[NQ * QS + q * QS + (r + 1) * TX + c];
+                    }
+                    flux_item(std::integral_constant<int, 1>{}, VL, VR, &FYs[r * TX + c], (TY + 1) * TX);
+                }
+            }
+        } else {
+            // (c) x- and y-faces of the plane.  Items go out in 64-wide chunks,
+            // one chunk per wave at a time; x items are padded to whole chunks so
+            // every chunk is a single direction and the solver is inlined with a
+            // compile-time frame.
+            for (int ch = wave; ch < NCHUNK; ch += TY) {
+                if (ch < NCHX) {
+                    const int it = ch * TX + tx;
+                    const bool valid = it < NFX;
+                    const int r = valid ? it / (TX + 1) : 0;
+                    const int f = valid ? it - r * (TX + 1) : 0;
+                    // cells f-2 .. f+1 of row r
+                    face_item(std::integral_constant<int, 0>{}, &P[(r + HY) * PX + f], 1,
+                              valid ? &FXs[r * (TX + 1) + f] : nullptr, TY * (TX + 1));
+                } else {
+                    const int it = (ch - NCHX) * TX + tx;
+                    const int r = it / TX, c = it - r * TX;
+                    // rows r-2 .. r+1 of column c
+                    face_item(std::integral_constant<int, 1>{}, &P[r * PX + c + H], PX, &FYs[r * TX + c],
+                              (TY + 1) * TX);
+                }
             }
         }
         __syncthreads();
