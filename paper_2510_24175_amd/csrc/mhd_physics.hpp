@@ -111,6 +111,15 @@ template <int LIM, typename T> __device__ __forceinline__ T limited_slope(T a, T
 // indicator tau5 = |beta0 - beta2|; their linear weights are mirror images,
 // (1, 6, 3)/10 on (S0, S1, S2) for the right face and (3, 6, 1)/10 for the
 // left, each scaled by 1 + tau5 / (beta_k + eps).
+//
+// FP64: the weights are multiplied through by (beta0+eps)(beta1+eps)(beta2+eps),
+// W_k = prod_{j != k}(beta_j + eps) (beta_k + eps + tau5), and both faces are
+// normalised with one division (the products stay within FP64 range for
+// indicators between eps and 1e60).  FP32: the reciprocals are the hardware
+// approximation and the ratio tau5/(beta_k + eps) is capped at 1e18 so that
+// the weights stay finite for jumps whose indicators exceed FLT_MAX * eps; the
+// cap only binds where two candidates are both 1e18 times smoother than
+// tau5, and then their face values agree far below FP32 resolution.
 template <typename T>
 __device__ __forceinline__ void wenoz_pair(T v0, T v1, T v2, T v3, T v4, T &rgt, T &lft)
 {
@@ -119,24 +128,42 @@ __device__ __forceinline__ void wenoz_pair(T v0, T v1, T v2, T v3, T v4, T &rgt,
     const T G1 = T(0.5) * (v1 - v3);
     const T G2 = T(1.5) * v2 - T(2) * v3 + T(0.5) * v4;
     const T c = T(13.0 / 12.0);
-    const T b0 = c * e0 * e0 + G0 * G0;
-    const T b1 = c * e1 * e1 + G1 * G1;
-    const T b2 = c * e2 * e2 + G2 * G2;
-    const T tau = Num<T>::abs(b0 - b2);
     const T eps = Num<T>::weno_eps;
-    const T r0 = tau * Num<T>::rcp(b0 + eps);
-    const T r1 = tau * Num<T>::rcp(b1 + eps);
-    const T r2 = tau * Num<T>::rcp(b2 + eps);
+    const T B0 = (c * e0 * e0 + G0 * G0) + eps;
+    const T B1 = (c * e1 * e1 + G1 * G1) + eps;
+    const T B2 = (c * e2 * e2 + G2 * G2) + eps;
+    const T tau = Num<T>::abs(B0 - B2);
     // candidate deviations from v2 at the two faces
     const T h0 = e0 * T(1.0 / 12.0), h1 = e1 * T(1.0 / 12.0), h2 = e2 * T(1.0 / 12.0);
     const T d0r = h0 + T(0.5) * G0, d0l = h0 - T(0.5) * G0;
     const T d1r = h1 - T(0.5) * G1, d1l = h1 + T(0.5) * G1;
     const T d2r = h2 - T(0.5) * G2, d2l = h2 + T(0.5) * G2;
-    const T a1 = T(0.6) + T(0.6) * r1;
-    const T a0r = T(0.1) + T(0.1) * r0, a2r = T(0.3) + T(0.3) * r2;
-    const T a0l = T(0.3) + T(0.3) * r0, a2l = T(0.1) + T(0.1) * r2;
-    rgt = v2 + (a0r * d0r + a1 * d1r + a2r * d2r) * Num<T>::rcp(a0r + a1 + a2r);
-    lft = v2 + (a0l * d0l + a1 * d1l + a2l * d2l) * Num<T>::rcp(a0l + a1 + a2l);
+    T a0r, a1, a2r, a0l, a2l;
+    if constexpr (sizeof(T) == 8) {
+        const T w0 = (B1 * B2) * (B0 + tau);
+        const T w1 = (B0 * B2) * (B1 + tau);
+        const T w2 = (B0 * B1) * (B2 + tau);
+        a1 = T(0.6) * w1;
+        a0r = T(0.1) * w0, a2r = T(0.3) * w2;
+        a0l = T(0.3) * w0, a2l = T(0.1) * w2;
+    } else {
+        const T m0 = Num<T>::min(tau * Num<T>::rcp(B0), T(1e18));
+        const T m1 = Num<T>::min(tau * Num<T>::rcp(B1), T(1e18));
+        const T m2 = Num<T>::min(tau * Num<T>::rcp(B2), T(1e18));
+        a1 = T(0.6) + T(0.6) * m1;
+        a0r = T(0.1) + T(0.1) * m0, a2r = T(0.3) + T(0.3) * m2;
+        a0l = T(0.3) + T(0.3) * m0, a2l = T(0.1) + T(0.1) * m2;
+    }
+    const T nr = a0r * d0r + a1 * d1r + a2r * d2r, sr = a0r + a1 + a2r;
+    const T nl = a0l * d0l + a1 * d1l + a2l * d2l, sl = a0l + a1 + a2l;
+    if constexpr (sizeof(T) == 8) {
+        const T inv = T(1) / (sr * sl);
+        rgt = v2 + nr * (sl * inv);
+        lft = v2 + nl * (sr * inv);
+    } else {
+        rgt = v2 + nr * Num<T>::rcp(sr);
+        lft = v2 + nl * Num<T>::rcp(sl);
+    }
 }
 
 // Fast magnetosonic speed from rho, p, |B|^2 and B_n^2:
