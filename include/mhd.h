@@ -140,7 +140,12 @@ mhd_status mhd_cfl_dt(mhd_ctx *ctx, const void *U, double out[2]);
  * alias Un.  U1_out (may be NULL) receives the stage-1 state, which the
  * adjoint reuses; otherwise library scratch is used.  The step also
  * reduces, on U_next, the CFL maxima and the FP64 sums read back by
- * mhd_step_info.  dt > 0, c_h > 0 when GLM is on, 0 < damp <= 1. */
+ * mhd_step_info.  With FP64 states every cell's speeds are formed in FP64;
+ * with FP32 states each thread picks, by FP32 estimates, the cells of its
+ * column with the largest speeds and reports their FP64 speeds, so the
+ * maxima are FP64 speeds of actual cells, within the estimate's rounding
+ * (~1e-6 relative) of the all-FP64 maxima.  dt > 0, c_h > 0 when GLM is
+ * on, 0 < damp <= 1. */
 mhd_status mhd_step(mhd_ctx *ctx, const void *Un, void *U_next, void *U1_out, double dt,
                     double c_h, double damp);
 

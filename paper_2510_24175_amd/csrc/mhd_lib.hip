@@ -73,7 +73,11 @@ struct Launch {
     int tiles_x, tiles_y, chunks, kz, nblocks;
 };
 
-Launch plan_stage(const mhd_ctx *ctx, int ty)
+// min_blocks: the grid size below which z chunks are shortened (each chunk
+// pays a warm-up of a few planes); the forward stages run two or three
+// workgroups per compute unit and want 2048, the adjoint runs one and
+// wants 512 (its warm-up is three full planes of z work).
+Launch plan_stage(const mhd_ctx *ctx, int ty, long long min_blocks = 2048)
 {
     Launch L;
     L.tiles_x = (int)((ctx->n[0] + TX - 1) / TX);
@@ -84,7 +88,7 @@ Launch plan_stage(const mhd_ctx *ctx, int ty)
         // long z chunks amortise the warm-up planes; shorter chunks when
         // the grid would otherwise leave compute units idle
         kz = 64;
-        while (kz > 4 && tiles * ((ctx->n[2] + kz - 1) / kz) < 2048) kz >>= 1;
+        while (kz > 4 && tiles * ((ctx->n[2] + kz - 1) / kz) < min_blocks) kz >>= 1;
     }
     L.kz = kz;
     L.chunks = (int)((ctx->n[2] + kz - 1) / kz);
@@ -200,7 +204,7 @@ mhd_status launch_adj_stage(mhd_ctx *ctx, const T *U, const double *lamp, const 
                             double *out, double dt, double ch, double damp)
 {
     constexpr int TY = adj_tile_rows<T, NDIM>();
-    const Launch L = plan_stage(ctx, TY);
+    const Launch L = plan_stage(ctx, TY, 512);
     AdjStageArgs<T> a;
     a.U = U;
     a.lamp = lamp;

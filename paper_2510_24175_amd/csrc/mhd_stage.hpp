@@ -86,6 +86,42 @@ __device__ __forceinline__ bool cell_speeds(const T *u, double gamma, const doub
     return ok;
 }
 
+// FP32 signal speeds of one FP32 cell state, used only to pick the cell
+// whose FP64 speeds a thread reports: ls = max_d (|v_d| + c_f,d)/dx_d,
+// lc = max_d (|v_d| + c_f,d).  The discriminant is formed from the
+// transverse field, (a^2 - b^2)^2 + 4 a^2 b_t^2, a sum of non-negative terms,
+// so the estimate carries only rounding of the order of ten FP32 ulps.
+// Returns false for rho <= 0, p <= 0 or non-finite values.
+template <int NDIM>
+__device__ __forceinline__ bool cell_speeds_f32(const float *u, float gamma, const float *idx, float &ls,
+                                                float &lc)
+{
+    const float rho = u[RHO];
+    const float ir = __builtin_amdgcn_rcpf(rho);
+    const float m[3] = {u[MX], u[MY], u[MZ]};
+    const float b[3] = {u[BX], u[BY], u[BZ]};
+    const float bb[3] = {b[0] * b[0], b[1] * b[1], b[2] * b[2]};
+    const float bsq = bb[0] + bb[1] + bb[2];
+    const float kin = 0.5f * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * ir;
+    const float p = (gamma - 1.0f) * (u[ENG] - kin - 0.5f * bsq);
+    const bool ok = (rho > 0.0f) & (rho < 1e30f) & (p > 0.0f) & (p < 1e30f);
+    const float a2 = gamma * p * ir;
+    const float b2 = bsq * ir;
+    const float dab = a2 - b2;
+    ls = 0.0f;
+    lc = 0.0f;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        const float bt2 = (bb[(d + 1) % 3] + bb[(d + 2) % 3]) * ir;
+        const float disc = dab * dab + 4.0f * a2 * bt2;
+        const float cf = __builtin_amdgcn_sqrtf(0.5f * (a2 + b2 + __builtin_amdgcn_sqrtf(disc)));
+        const float lam = __builtin_fabsf(m[d] * ir) + cf;
+        ls = __builtin_fmaxf(ls, lam * idx[d]);
+        lc = __builtin_fmaxf(lc, lam);
+    }
+    return ok;
+}
+
 template <typename T>
 __device__ __forceinline__ void load_cell(const T *__restrict__ U, long long ncell, long long c, T *u)
 {
@@ -298,6 +334,10 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
     }
 
     double smax = 0.0, cmax = 0.0;
+    // FP32 states: the z index of this thread's cells with the largest FP32
+    // estimates of the two maxima (their FP64 speeds are taken at the end)
+    float best_s = -1.0f, best_c = -1.0f;
+    int k_s = -1, k_c = -1;
     double sum[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) sum[q] = 0.0;
@@ -482,10 +522,16 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             if (LAST) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) sum[q] += (double)out[q];
-                // FP64 signal speeds of every updated cell (a filter on an FP32
-                // estimate measured slower: some lane of a wave nearly always
-                // needs the exact value)
-                ok &= cell_speeds<T, NDIM>(out, a.gamma_d, a.idx_d, smax, cmax);
+                if constexpr (sizeof(T) == 8) {
+                    ok &= cell_speeds<T, NDIM>(out, a.gamma_d, a.idx_d, smax, cmax);
+                } else {
+                    float ls, lc;
+                    ok &= cell_speeds_f32<NDIM>(out, a.ph.gamma, a.idx, ls, lc);
+                    k_s = ls > best_s ? k : k_s;
+                    best_s = __builtin_fmaxf(best_s, ls);
+                    k_c = lc > best_c ? k : k_c;
+                    best_c = __builtin_fmaxf(best_c, lc);
+                }
             }
         }
         if (NDIM == 3) {
@@ -497,6 +543,20 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
         }
     }
 
+    if constexpr (LAST && sizeof(T) == 4) {
+        // FP64 speeds of the selected cells, re-read from this thread's own
+        // output (it stored them above)
+        if (k_s >= 0) {
+            T u[NQ];
+            load_cell(a.uout, a.ncell, zoff(k_s) + own, u);
+            ok &= cell_speeds<T, NDIM>(u, a.gamma_d, a.idx_d, smax, cmax);
+        }
+        if (k_c >= 0 && k_c != k_s) {
+            T u[NQ];
+            load_cell(a.uout, a.ncell, zoff(k_c) + own, u);
+            ok &= cell_speeds<T, NDIM>(u, a.gamma_d, a.idx_d, smax, cmax);
+        }
+    }
     if (!ok) atomicOr(a.flag, 1);
 
     if (LAST) {
