@@ -143,12 +143,15 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Waves per SIMD the FP32 kernels are compiled for: PLM, register budget
-// 168 (with 4-wave workgroups three of them share a compute unit); WENO-Z,
-// whose workgroups hold twice the LDS (two per compute unit), 256.
+// Waves per SIMD the kernels are compiled for.  FP32 PLM: register budget
+// 168 (with 4-wave workgroups three of them share a compute unit); FP32
+// WENO-Z, whose 8-row workgroups take 124 KB of LDS (one per compute unit),
+// 256.  FP64 PLM: 2 (256 registers; the HLLD kernels spill 26-83 of them,
+// and still run 11% faster than at one wave per SIMD without spills).  FP64
+// WENO-Z: 1 (140 KB of LDS allows one 4-wave workgroup per compute unit).
 template <typename T, int LIM> constexpr int stage_min_waves()
 {
-    return sizeof(T) == 4 ? (LIM == LIM_WENOZ ? 2 : 3) : 1;
+    return sizeof(T) == 4 ? (LIM == LIM_WENOZ ? 2 : 3) : (LIM == LIM_WENOZ ? 1 : 2);
 }
 
 // Stage kinds of the Runge-Kutta integrators (KIND): 1 U1 = Un + dt L(Un)
