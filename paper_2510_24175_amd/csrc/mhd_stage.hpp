@@ -1,25 +1,29 @@
 // Fused Runge-Kutta stage kernel: ghost fill (index remap), conservative ->
-// primitive, PLM reconstruction, GLM + Riemann fluxes on every face, flux
-// divergence and the stage combine, in one pass over the grid.
+// primitive, reconstruction (PLM or WENO-Z), GLM + Riemann fluxes on every
+// face, flux divergence and the stage combine, in one pass over the grid.
 //
 // Work decomposition (gfx950, wave64):
 //   * a workgroup owns a tile of TX = 64 (x) by TY (y) columns and marches
 //     along z over a chunk of planes [k0, k1);
 //   * one wave per tile row, one lane per column; the primitive state of
-//     the current plane, with a 2-cell x/y halo, sits in LDS;
-//   * z-faces come from a per-lane register window (V(k), V(k+1) and the
-//     limited slope of V(k)) slid along the march, so every z-face flux is
+//     the current plane, with an x/y halo of the stencil's half width (2
+//     cells PLM, 3 WENO-Z), sits in LDS;
+//   * z-faces come from a per-lane register window slid along the march
+//     (PLM: V(k), V(k+1) and the limited slope of V(k); WENO-Z: V(k-1) ..
+//     V(k+2) and the upper face value of cell k), so every z-face flux is
 //     computed once per chunk plus one warm-up face;
 //   * x- and y-faces of the plane are a flat work list of
 //     TY(TX+1) + (TY+1)TX items spread over the workgroup; their fluxes
 //     go through LDS to the cells on both sides, so each face is solved
-//     once per tile;
+//     once per tile.  WENO-Z first reconstructs every cell the faces need
+//     once per direction (both of its face values) into LDS;
 //   * ghost cells are never stored: out-of-range coordinates are mapped to
 //     interior cells by the boundary rule when addresses are formed.
-// Stage 1 writes U1 = Un + dt L(Un); stage 2 writes
-// U_next = (Un + U1 + dt L(U1)) / 2 with psi damped, and reduces on U_next
-// the CFL maxima (FP64) and the FP64 conservation sums into per-block
-// partials.
+// Stage kinds (KIND): 1 writes U1 = Un + dt L(Un); 2 the SSP-RK2 result
+// (Un + U1 + dt L(U1)) / 2; 3 the SSP-RK3 stage 3/4 Un + 1/4 (U1 + dt L(U1));
+// 4 the SSP-RK3 result 1/3 Un + 2/3 (U2 + dt L(U2)).  The last stage of
+// either integrator damps psi and reduces on its output the CFL maxima and
+// the FP64 conservation sums into per-block partials.
 #pragma once
 
 #include <type_traits>
@@ -35,9 +39,9 @@ constexpr int NPART = 11;
 
 template <typename T> struct StageArgs {
     const T *uin;   // state the fluxes are built from (Un or U1)
-    const T *un;    // Un (stage 2 combine); equals uin in stage 1
-    T *uout;        // U1 (stage 1) or U_next (stage 2)
-    double *part;   // stage 2: NPART x nblocks partials
+    const T *un;    // Un (later stages' combine); equals uin in stage 1
+    T *uout;        // this stage's output (U1, U2 or U_next)
+    double *part;   // last stage: NPART x nblocks partials
     int *flag;      // non-physical flag
     int nx, ny, nz; // interior cells
     long long nxy;  // nx*ny

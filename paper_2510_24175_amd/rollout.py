@@ -4,7 +4,8 @@ Per step: dt and c_h come from the CFL reduction of the current state (the
 standalone reduction for the first step, afterwards the maxima the previous
 step already reduced on its output), dt is clipped so that t does not pass
 t_end, the GLM decay factor exp(-alpha c_h dt / dh_min) is formed on the
-host in FP64, and one SSP-RK2 step runs on the device.
+host in FP64, and one Runge-Kutta step (SSP-RK2 or SSP-RK3, as the
+context is configured) runs on the device.
 """
 import torch
 
