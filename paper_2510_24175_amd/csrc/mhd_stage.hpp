@@ -191,17 +191,20 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
     constexpr int NRX = WENO ? TY * NXE : 0;             // x reconstruction items
     constexpr int NRY = (WENO && NDIM >= 2) ? NYE * TX : 0;
     constexpr int NRCH = (NRX + NRY + TX - 1) / TX;      // their 64-wide chunks
-    // LDS: PLM [P][FX][FY]; WENO-Z [P, with FX FY over it once P is used][EX][EY]
+    // LDS: [P][FX][FY] and, for WENO-Z, [EX][EY]; when that exceeds the 160 KB
+    // of a compute unit (FP64), FX and FY go over P once P is used, and the
+    // next plane's loads wait for the update (one more barrier per plane)
     constexpr int SZP = NQ * PLANE;
     constexpr int SZFX = NQ * TY * (TX + 1);
     constexpr int SZFY = NDIM >= 2 ? NQ * (TY + 1) * TX : 0;
-    constexpr int SZEX = 2 * NQ * TY * NXE;
-    constexpr int SZEY = 2 * NQ * NYE * TX;
-    constexpr int OFX = WENO ? 0 : SZP;
+    constexpr int SZEX = WENO ? 2 * NQ * TY * NXE : 0;
+    constexpr int SZEY = (WENO && NDIM >= 2) ? 2 * NQ * NYE * TX : 0;
+    constexpr bool ALIAS = WENO && (SZP + SZFX + SZFY + SZEX + SZEY) * (int)sizeof(T) > 160 * 1024;
+    constexpr int OFX = ALIAS ? 0 : SZP;
     constexpr int OFY = OFX + SZFX;
-    constexpr int OEX = WENO ? (SZP > SZFX + SZFY ? SZP : SZFX + SZFY) : OFY + SZFY;
-    constexpr int OEY = OEX + (WENO ? SZEX : 0);
-    constexpr int SZL = OEY + ((WENO && NDIM >= 2) ? SZEY : 0);
+    constexpr int OEX = ALIAS ? (SZP > SZFX + SZFY ? SZP : SZFX + SZFY) : OFY + SZFY;
+    constexpr int OEY = OEX + SZEX;
+    constexpr int SZL = OEY + SZEY;
 
     __shared__ T lds[SZL];
     T *const P = lds;
@@ -351,8 +354,8 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
 
     for (int k = k0; k < k1; ++k) {
         const long long zk = zoff(k);
-        // WENO-Z: the fluxes of the previous plane sit where P goes
-        if (WENO && k > k0) __syncthreads();
+        // the fluxes of the previous plane sit where P goes
+        if (ALIAS && k > k0) __syncthreads();
         // (a) primitives of plane k into LDS: own column and halo cell
 #pragma unroll
         for (int q = 0; q < NQ; ++q) P[q * PLANE + own_slot] = Wz[ZC][q];
@@ -437,7 +440,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             __syncthreads();
             // (c1) face fluxes from the edge values: x face f of row r between
             // cells f-1 and f, y face r of column c between rows r-1 and r;
-            // the fluxes overwrite P
+            // (the fluxes overwrite P when the LDS is aliased)
             for (int ch = wave; ch < NCHUNK; ch += TY) {
                 T VL[NQ], VR[NQ];
                 if (ch < NCHX) {
