@@ -10,7 +10,9 @@ FP64) and holds the oracle's own time loop:
   parabolic part applied as an exact decay once per step), then one SSP-RK2
   or SSP-RK3 step (Shu & Osher 1988).
 
-Arrays are numpy float64, structure-of-arrays ``[9][nz][ny][nx]``.
+Arrays are numpy float64, structure-of-arrays ``[9][nz][ny][nx]``; with
+constrained transport (setup ``"ct": True``) ``[12][nz][ny][nx]``, the last
+three the face-centred field on each cell's lower x, y and z face.
 """
 import ctypes
 import math
@@ -39,7 +41,7 @@ class _Cfg(ctypes.Structure):
         ("cfl", ctypes.c_double),
         ("glm_alpha", ctypes.c_double),
         ("time_order", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("ct", ctypes.c_int32),
     ]
 
 
@@ -121,8 +123,10 @@ class Oracle:
         c.cfl = float(setup["cfl"])
         c.glm_alpha = float(setup.get("glm_alpha", 0.1))
         c.time_order = int(setup.get("time_order", 2))
+        c.ct = 1 if setup.get("ct", False) else 0
         self.cfg = c
-        self.shape = (9, int(setup["n"][2]), int(setup["n"][1]), int(setup["n"][0]))
+        self.nstate = 12 if c.ct else 9
+        self.shape = (self.nstate, int(setup["n"][2]), int(setup["n"][1]), int(setup["n"][0]))
         self.ndim = c.ndim
         self.dx = [(c.hi[d] - c.lo[d]) / c.n[d] for d in range(3)]
         self.dh_min = min(self.dx[d] for d in range(c.ndim))
@@ -155,7 +159,7 @@ class Oracle:
         return L
 
     def damp(self, dt, ch):
-        if not self.setup.get("glm", True):
+        if not self.setup.get("glm", True) or self.cfg.ct:
             return 1.0
         return math.exp(-float(self.setup.get("glm_alpha", 0.1)) * ch * dt / self.dh_min)
 
@@ -171,10 +175,23 @@ class Oracle:
         return (out, u1) if want_u1 else out
 
     def sums(self, U):
+        """Sums of the 9 cell-centred components times the cell volume."""
         U = _f64(U).reshape(self.shape)
         out = np.zeros(9)
         _check(lib().orc_sums(ctypes.byref(self.cfg), _p(U), _p(out)), "sums")
         return out
+
+    def div_b(self, U):
+        """Divergence of the face field of each cell (constrained transport):
+        sum over axes of (b_d(upper face) - b_d(lower face)) / dx_d."""
+        U = _f64(U).reshape(self.shape)
+        if not self.cfg.ct:
+            raise OracleError("div_b needs a constrained-transport state")
+        div = np.zeros(self.shape[1:])
+        for d, ax in ((0, 2), (1, 1), (2, 0)):
+            b = U[9 + d]
+            div += (np.roll(b, -1, axis=ax) - b) / self.dx[d]
+        return div
 
     # -- time loop -------------------------------------------------------
     def run(self, U, nsteps=None, t_end=None, t0=0.0, record=None):

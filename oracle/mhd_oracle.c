@@ -40,9 +40,19 @@
  *              damp = exp(-alpha c_h dt / dh_min) supplied by the caller.
  *   CFL      : dt = C / max_{cells,d} (|v_d| + c_f,d) / dx_d,
  *              c_h = max_{cells,d} (|v_d| + c_f,d).
+ *   CT       : (the paper's weak-scaling runs) constrained transport (Evans &
+ *              Hawley 1988) in 3D on periodic grids, GLM off: the field lives
+ *              on the cell faces, the normal field of each Riemann problem is
+ *              the face value, edge EMFs are the arithmetic mean of the four
+ *              face fluxes around the edge (Balsara & Spicer 1999; the paper
+ *              also cites the upwind CT of Londrillo & Del Zanna 2004, whose
+ *              EMF it does not print), faces advance by the discrete curl of
+ *              the EMFs with the same Runge-Kutta stages, and the cell field
+ *              is the mean of each cell's two faces per axis.
  *
- * External arrays are structure-of-arrays, shape [9][nz][ny][nx], x fastest,
- * interior cells only.  Internally the oracle uses its own padded
+ * External arrays are structure-of-arrays, shape [9][nz][ny][nx] ([12] with
+ * constrained transport: the face field on each cell's lower x, y, z face
+ * in slots 9..11), x fastest, interior cells only.  Internally the oracle uses its own padded
  * array-of-structures with explicit ghost cells.
  *
  * Status codes: 0 ok, 1 non-physical state (rho<=0, p<=0 or non-finite),
@@ -77,8 +87,15 @@ typedef struct {
     double cfl;
     double glm_alpha;
     int32_t time_order; /* 2: SSP-RK2, 3: SSP-RK3 */
-    int32_t reserved;
+    int32_t ct;         /* 1: constrained transport (face-centred B), 0: cell-centred B */
 } orc_cfg;
+
+/* State components: 9 cell-centred (RHO .. PSI); with constrained transport
+ * three more, the face-centred field bx, by, bz on each cell's lower x, y and
+ * z face (FBX, FBY, FBZ), and the cell-centred B is the average of the two
+ * faces of the cell along each axis. */
+enum { FBX = 9, FBY = 10, FBZ = 11 };
+static int nstate(const orc_cfg *cfg) { return cfg->ct ? 12 : NV; }
 
 /* ------------------------------------------------------------------ */
 /* pointwise physics                                                    */
@@ -408,12 +425,16 @@ static void glm_interface(double bnL, double bnR, double psiL, double psiR, doub
 /* Full interface flux from two unrotated primitive face states (9 comps):
  * GLM interface solve, then the MHD solver on the 8 MHD components with
  * B_n replaced by B_n*, then F(B_n) = psi*, F(psi) = c_h^2 B_n*.          */
-static void face_flux(const orc_cfg *cfg, int d, const double *VL, const double *VR,
-                      double ch, double *F)
+static void face_flux_bn(const orc_cfg *cfg, int d, const double *VL, const double *VR,
+                         double ch, const double *bn_face, double *F)
 {
     double bnL = VL[BX + d], bnR = VR[BX + d];
     double bns, psis;
-    if (cfg->glm) {
+    if (bn_face) {
+        /* constrained transport: the normal field is the face's own value */
+        bns = *bn_face;
+        psis = 0.0;
+    } else if (cfg->glm) {
         double g[2];
         glm_interface(bnL, bnR, VL[PSI], VR[PSI], ch, g);
         bns = g[0];
@@ -449,13 +470,19 @@ static void face_flux(const orc_cfg *cfg, int d, const double *VL, const double 
     F[ENG] = f[4];
     F[BX + axis_of(d, 1)] = f[6];
     F[BX + axis_of(d, 2)] = f[7];
-    if (cfg->glm) {
+    if (cfg->glm && !bn_face) {
         F[BX + d] = psis;
         F[PSI] = ch * ch * bns;
     } else {
         F[BX + d] = 0.0;
         F[PSI] = 0.0;
     }
+}
+
+static void face_flux(const orc_cfg *cfg, int d, const double *VL, const double *VR,
+                      double ch, double *F)
+{
+    face_flux_bn(cfg, d, VL, VR, ch, NULL, F);
 }
 
 /* ------------------------------------------------------------------ */
@@ -542,8 +569,12 @@ static int load_prims(const orc_cfg *cfg, const grid *G, const double *U, double
 /* L(U) for all interior cells, SoA [9][nz][ny][nx].  W holds primitives
  * with ghosts.  Each active direction is handled in turn: the flux through
  * every interface of a line is computed once and differenced.            */
+/* With constrained transport (U non-NULL) the normal field of each face is
+ * the face value held in U, and the two transverse field fluxes of every
+ * cell's lower face along each axis go to Fl[6][nc]: (x face: F(By), F(Bz)),
+ * (y face: F(Bx), F(Bz)), (z face: F(Bx), F(By)). */
 static void rhs_from_prims(const orc_cfg *cfg, const grid *G, const double *W, double ch,
-                           double *L)
+                           double *L, const double *U, double *Fl)
 {
     int64_t nx = G->n[0], ny = G->n[1], nz = G->n[2], nc = nx * ny * nz;
     memset(L, 0, sizeof(double) * NV * nc);
@@ -581,7 +612,25 @@ static void rhs_from_prims(const orc_cfg *cfg, const grid *G, const double *W, d
                                 VR[q] = B[q] - 0.5 * sb;
                             }
                         }
-                        face_flux(cfg, d, VL, VR, ch, face == 0 ? Fm : Fp);
+                        if (U) {
+                            /* the lower face is this cell's, the upper one the
+                             * next cell's along d (periodic) */
+                            int64_t ii = i, jj = j, kk = k;
+                            if (face == 1) {
+                                if (d == 0) ii = (i + 1) % nx;
+                                if (d == 1) jj = (j + 1) % ny;
+                                if (d == 2) kk = (k + 1) % nz;
+                            }
+                            const double bn = U[(FBX + d) * nc + (kk * ny + jj) * nx + ii];
+                            face_flux_bn(cfg, d, VL, VR, ch, &bn, face == 0 ? Fm : Fp);
+                        } else {
+                            face_flux(cfg, d, VL, VR, ch, face == 0 ? Fm : Fp);
+                        }
+                    }
+                    if (Fl) {
+                        /* the two transverse components in increasing order */
+                        Fl[(2 * d) * nc + c] = Fm[d == 0 ? BY : BX];
+                        Fl[(2 * d + 1) * nc + c] = Fm[d == 2 ? BY : BZ];
                     }
                     for (int q = 0; q < NV; ++q) L[q * nc + c] -= (Fp[q] - Fm[q]) / dx;
                 }
@@ -590,15 +639,78 @@ static void rhs_from_prims(const orc_cfg *cfg, const grid *G, const double *W, d
     }
 }
 
+/* Constrained transport (Evans & Hawley 1988), edge EMFs as the arithmetic
+ * mean of the four face fluxes around each edge (Balsara & Spicer 1999),
+ * E = -v x B so that F_x(By) = -Ez, F_y(Bx) = Ez, F_y(Bz) = -Ex, F_z(By) = Ex,
+ * F_z(Bx) = -Ey, F_x(Bz) = Ey.  E[3][nc] holds the EMFs on each cell's lower
+ * edges: Ex at (j-1/2, k-1/2), Ey at (i-1/2, k-1/2), Ez at (i-1/2, j-1/2).
+ * The face rates dB/dt = -curl E are written to L[FBX..FBZ]. */
+static void ct_face_rates(const orc_cfg *cfg, const double *Fl, double *L)
+{
+    int64_t nx = cfg->n[0], ny = cfg->n[1], nz = cfg->n[2], nc = nx * ny * nz;
+    double dx = (cfg->hi[0] - cfg->lo[0]) / (double)nx;
+    double dy = (cfg->hi[1] - cfg->lo[1]) / (double)ny;
+    double dz = (cfg->hi[2] - cfg->lo[2]) / (double)nz;
+    const double *FxBy = Fl, *FxBz = Fl + nc, *FyBx = Fl + 2 * nc, *FyBz = Fl + 3 * nc;
+    const double *FzBx = Fl + 4 * nc, *FzBy = Fl + 5 * nc;
+    double *E = (double *)malloc(sizeof(double) * 3 * nc);
+    if (!E) return;
+#define CI(i, j, k) ((((k) + nz) % nz * ny + ((j) + ny) % ny) * nx + ((i) + nx) % nx)
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t c = CI(i, j, k);
+                E[c] = 0.25 * (-FyBz[CI(i, j, k - 1)] - FyBz[c] + FzBy[CI(i, j - 1, k)] + FzBy[c]);
+                E[nc + c] = 0.25 * (FxBz[CI(i, j, k - 1)] + FxBz[c] - FzBx[CI(i - 1, j, k)] - FzBx[c]);
+                E[2 * nc + c] = 0.25 * (-FxBy[CI(i, j - 1, k)] - FxBy[c] + FyBx[CI(i - 1, j, k)] + FyBx[c]);
+            }
+    const double *Ex = E, *Ey = E + nc, *Ez = E + 2 * nc;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t c = CI(i, j, k);
+                L[FBX * nc + c] = -((Ez[CI(i, j + 1, k)] - Ez[c]) / dy - (Ey[CI(i, j, k + 1)] - Ey[c]) / dz);
+                L[FBY * nc + c] = -((Ex[CI(i, j, k + 1)] - Ex[c]) / dz - (Ez[CI(i + 1, j, k)] - Ez[c]) / dx);
+                L[FBZ * nc + c] = -((Ey[CI(i + 1, j, k)] - Ey[c]) / dx - (Ex[CI(i, j + 1, k)] - Ex[c]) / dy);
+            }
+    free(E);
+}
+
+/* cell-centred B of every cell from its two faces along each axis */
+static void ct_cell_field(const orc_cfg *cfg, double *U)
+{
+    int64_t nx = cfg->n[0], ny = cfg->n[1], nz = cfg->n[2], nc = nx * ny * nz;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t c = CI(i, j, k);
+                U[BX * nc + c] = 0.5 * (U[FBX * nc + c] + U[FBX * nc + CI(i + 1, j, k)]);
+                U[BY * nc + c] = 0.5 * (U[FBY * nc + c] + U[FBY * nc + CI(i, j + 1, k)]);
+                U[BZ * nc + c] = 0.5 * (U[FBZ * nc + c] + U[FBZ * nc + CI(i, j, k + 1)]);
+            }
+#undef CI
+}
+
 static int rhs(const orc_cfg *cfg, const double *U, double ch, double *L)
 {
     grid G;
     grid_make(cfg, &G);
+    int64_t nc = cfg->n[0] * cfg->n[1] * cfg->n[2];
     double *W = (double *)malloc(sizeof(double) * NV * G.cells);
-    if (!W) return 2;
+    double *Fl = cfg->ct ? (double *)malloc(sizeof(double) * 6 * nc) : NULL;
+    if (!W || (cfg->ct && !Fl)) {
+        free(W);
+        free(Fl);
+        return 2;
+    }
     int ok = load_prims(cfg, &G, U, W);
-    if (ok) rhs_from_prims(cfg, &G, W, ch, L);
+    if (ok) rhs_from_prims(cfg, &G, W, ch, L, cfg->ct ? U : NULL, Fl);
+    if (ok && cfg->ct) ct_face_rates(cfg, Fl, L);
     free(W);
+    free(Fl);
     return ok ? 0 : 1;
 }
 
@@ -616,19 +728,35 @@ static int cfg_ok(const orc_cfg *cfg)
     }
     if (cfg->limiter < ORC_MINMOD || cfg->limiter > ORC_WENOZ) return 0;
     if (cfg->time_order != 2 && cfg->time_order != 3) return 0;
+    if (cfg->ct != 0 && cfg->ct != 1) return 0;
+    if (cfg->ct) {
+        /* three-dimensional, periodic, no GLM */
+        if (cfg->ndim != 3 || cfg->glm) return 0;
+        for (int d = 0; d < 3; ++d)
+            if (cfg->bc[d][0] != ORC_PERIODIC || cfg->bc[d][1] != ORC_PERIODIC) return 0;
+    }
     return cfg->gamma > 1.0;
 }
 
 static int64_t ncells(const orc_cfg *cfg) { return cfg->n[0] * cfg->n[1] * cfg->n[2]; }
 
+/* With constrained transport V and U carry the face field in slots
+ * FBX..FBZ; the cell-centred B of U (and the B entering E) is the average of
+ * the faces, whatever V holds in BX..BZ. */
 int orc_prim_to_cons(const orc_cfg *cfg, const double *V, double *U)
 {
     if (!cfg_ok(cfg)) return 2;
     int64_t nc = ncells(cfg);
+    if (cfg->ct) {
+        for (int q = FBX; q <= FBZ; ++q) memcpy(&U[q * nc], &V[q * nc], sizeof(double) * nc);
+        ct_cell_field(cfg, U);
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < nc; ++c) {
         double v[NV], u[NV];
         for (int q = 0; q < NV; ++q) v[q] = V[q * nc + c];
+        if (cfg->ct)
+            for (int q = BX; q <= BZ; ++q) v[q] = U[q * nc + c];
         prim_to_cons(v, cfg->gamma, u);
         for (int q = 0; q < NV; ++q) U[q * nc + c] = u[q];
     }
@@ -650,6 +778,8 @@ int orc_cons_to_prim(const orc_cfg *cfg, const double *U, double *V)
         }
         for (int q = 0; q < NV; ++q) V[q * nc + c] = v[q];
     }
+    if (cfg->ct)
+        for (int q = FBX; q <= FBZ; ++q) memcpy(&V[q * nc], &U[q * nc], sizeof(double) * nc);
     return ok ? 0 : 1;
 }
 
@@ -689,12 +819,14 @@ int orc_rhs(const orc_cfg *cfg, const double *U, double ch, double *L)
 }
 
 /* One SSP-RK2 or SSP-RK3 step with GLM damping.  U1_out (the first stage
- * state) may be NULL. */
+ * state) may be NULL.  With constrained transport the face field takes the
+ * same stage combinations and every stage's cell-centred B is then re-formed
+ * from the faces. */
 int orc_step(const orc_cfg *cfg, const double *Un, double *Unext, double *U1_out, double dt,
              double ch, double damp)
 {
     if (!cfg_ok(cfg) || Un == Unext) return 2;
-    int64_t nc = ncells(cfg), nt = NV * nc;
+    int64_t nc = ncells(cfg), nt = nstate(cfg) * nc;
     double *L = (double *)malloc(sizeof(double) * nt);
     double *U1 = (double *)malloc(sizeof(double) * nt);
     if (!L || !U1) {
@@ -706,6 +838,7 @@ int orc_step(const orc_cfg *cfg, const double *Un, double *Unext, double *U1_out
     if (st == 0) {
 #pragma omp parallel for schedule(static)
         for (int64_t a = 0; a < nt; ++a) U1[a] = Un[a] + dt * L[a];
+        if (cfg->ct) ct_cell_field(cfg, U1);
         st = rhs(cfg, U1, ch, L);
     }
     if (st == 0 && cfg->time_order == 3) {
@@ -713,16 +846,19 @@ int orc_step(const orc_cfg *cfg, const double *Un, double *Unext, double *U1_out
         /* U2 = 3/4 Un + 1/4 (U1 + dt L(U1)), stored over U1 */
 #pragma omp parallel for schedule(static)
         for (int64_t a = 0; a < nt; ++a) U1[a] = 0.75 * Un[a] + 0.25 * (U1[a] + dt * L[a]);
+        if (cfg->ct) ct_cell_field(cfg, U1);
         st = rhs(cfg, U1, ch, L);
         if (st == 0) {
 #pragma omp parallel for schedule(static)
             for (int64_t a = 0; a < nt; ++a)
                 Unext[a] = Un[a] / 3.0 + 2.0 / 3.0 * (U1[a] + dt * L[a]);
+            if (cfg->ct) ct_cell_field(cfg, Unext);
             for (int64_t c = 0; c < nc; ++c) Unext[PSI * nc + c] *= damp;
         }
     } else if (st == 0) {
 #pragma omp parallel for schedule(static)
         for (int64_t a = 0; a < nt; ++a) Unext[a] = 0.5 * (Un[a] + U1[a] + dt * L[a]);
+        if (cfg->ct) ct_cell_field(cfg, Unext);
         for (int64_t c = 0; c < nc; ++c) Unext[PSI * nc + c] *= damp;
         if (U1_out) memcpy(U1_out, U1, sizeof(double) * nt);
     }

@@ -327,3 +327,83 @@ def orszag_tang_3d(n, eps=0.2, riemann="hlld", cfl=0.3, limiter="wenoz", time_or
     V[6] = b0 * s4x[None, None, :]
     s["eps"] = float(eps)
     return s, V
+
+
+# ------------------------------------------- constrained transport -------
+#
+# With constrained transport the state carries the face-centred field on each
+# cell's lower x, y and z face as three more components (12 in all), and the
+# cell-centred B is the mean of the two faces of a cell along each axis.  The
+# initial face fields below have zero discrete divergence: either each face
+# component is independent of its own coordinate, or the field is the
+# discrete curl of an edge-centred vector potential.
+
+def _face_coords(setup):
+    """Cell-centre and lower-face coordinate arrays per axis."""
+    out = []
+    for d in range(3):
+        n = setup["n"][d]
+        lo, hi = setup["lo"][d], setup["hi"][d]
+        h = (hi - lo) / n
+        out.append((lo + (np.arange(n) + 0.5) * h, lo + np.arange(n) * h, h))
+    return out
+
+
+def _with_faces(V, faces):
+    W = np.zeros((12,) + V.shape[1:])
+    W[:9] = V
+    W[9:] = faces
+    return W
+
+
+def orszag_tang_3d_ct(n, eps=0.2, riemann="hlld", cfl=0.3, limiter="wenoz", time_order=3,
+                      t_end=None):
+    """The 3D Orszag-Tang vortex of ``orszag_tang_3d`` for constrained
+    transport (GLM off): face fields bx = -B0 sin 2pi y, by = B0 sin 4pi x,
+    bz = 0 sampled on the faces (each independent of its own coordinate, so
+    the discrete divergence is exactly zero)."""
+    s, V = orszag_tang_3d(n, eps=eps, riemann=riemann, cfl=cfl, limiter=limiter,
+                          time_order=time_order, t_end=t_end)
+    s["name"], s["ct"], s["glm"] = "orszag_tang_3d_ct", True, False
+    (xc, _, _), (yc, _, _), _ = _face_coords(s)
+    b0 = 1.0 / math.sqrt(4 * math.pi)
+    nx, ny, nz = s["n"]
+    faces = np.zeros((3, nz, ny, nx))
+    faces[0] = (-b0 * np.sin(2 * math.pi * yc))[None, :, None]
+    faces[1] = (b0 * np.sin(4 * math.pi * xc))[None, None, :]
+    return s, _with_faces(V, faces)
+
+
+def cpa_wave_3d_ct(n, amplitude=0.1, riemann="hlld", cfl=0.3, limiter="wenoz", time_order=3):
+    """The diagonal circularly polarised Alfven wave of ``cpa_wave_3d`` for
+    constrained transport: the face field is b0 khat plus the discrete curl
+    of the edge-centred potential A = a/(2 pi |k|) (sin phi e1 + cos phi e2),
+    whose continuous curl is the wave's perturbation a (sin phi e1 +
+    cos phi e2)."""
+    s, V = cpa_wave_3d(n, amplitude=amplitude, riemann=riemann, cfl=cfl, limiter=limiter,
+                       time_order=time_order)
+    s["name"], s["ct"], s["glm"] = "cpa3d_ct", True, False
+    k = np.array([1.0, 1.0, 1.0])
+    kn = np.linalg.norm(k)
+    kh = k / kn
+    ref = np.array([0.0, 0.0, 1.0]) if abs(kh[2]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(ref, kh)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(kh, e1)
+    (xc, xf, dx), (yc, yf, dy), (zc, zf, dz) = _face_coords(s)
+    c = amplitude / (2 * math.pi * kn)
+
+    def pot(comp, X, Y, Z):
+        Z3, Y3, X3 = np.meshgrid(Z, Y, X, indexing="ij")
+        phi = 2 * math.pi * (k[0] * X3 + k[1] * Y3 + k[2] * Z3)
+        return c * (np.sin(phi) * e1[comp] + np.cos(phi) * e2[comp])
+
+    Ax = pot(0, xc, yf, zf)  # x edges: (x_i, y_{j-1/2}, z_{k-1/2})
+    Ay = pot(1, xf, yc, zf)  # y edges: (x_{i-1/2}, y_j, z_{k-1/2})
+    Az = pot(2, xf, yf, zc)  # z edges: (x_{i-1/2}, y_{j-1/2}, z_k)
+    up = lambda a, ax: np.roll(a, -1, axis=ax)  # value at the next edge along an axis
+    faces = np.empty((3,) + Ax.shape)
+    faces[0] = kh[0] + (up(Az, 1) - Az) / dy - (up(Ay, 0) - Ay) / dz
+    faces[1] = kh[1] + (up(Ax, 0) - Ax) / dz - (up(Az, 2) - Az) / dx
+    faces[2] = kh[2] + (up(Ay, 2) - Ay) / dx - (up(Ax, 1) - Ax) / dy
+    return s, _with_faces(V, faces)

@@ -1,0 +1,123 @@
+"""Pins of the oracle's constrained transport (the divergence control of
+the paper's weak-scaling runs, section "Results for gPLUTO"; Evans & Hawley
+1988), edge EMFs as the arithmetic mean of the four face fluxes around
+each edge (Balsara & Spicer 1999).
+
+* the discrete divergence of the face field stays at rounding, for initial
+  fields whose face divergence is zero (a face component independent of its
+  own coordinate, or the discrete curl of an edge potential), whatever the
+  EMFs are - it pins the face update as a discrete curl;
+* mass, momentum, energy and the mean field are conserved on periodic grids;
+* uniform states are fixed points (bitwise with SSP-RK2);
+* the 3D Orszag-Tang vortex keeps its half-turn symmetry about the z axis
+  (face components move with their faces);
+* the diagonal circularly polarised Alfven wave converges at second order
+  (the staggered update is second order) - a wrong sign or edge in any EMF
+  term breaks it, since the diagonal wave drives all three.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import coracle as C
+from paper_2510_24175_amd import workloads as W
+
+
+def _scheme(s, limiter, time_order):
+    s = dict(s)
+    s["limiter"], s["time_order"] = limiter, time_order
+    return s
+
+
+@pytest.mark.parametrize("limiter,time_order", [("wenoz", 3), ("minmod", 2)])
+@pytest.mark.parametrize("gen", ["ot", "cpa"])
+def test_face_divergence_stays_at_rounding(gen, limiter, time_order):
+    if gen == "ot":
+        s, V = W.orszag_tang_3d_ct((16, 12, 10))
+    else:
+        s, V = W.cpa_wave_3d_ct((12, 12, 12))
+    s = _scheme(s, limiter, time_order)
+    o = C.Oracle(s)
+    U0 = o.prim_to_cons(V)
+    U, _, _ = o.run(U0, nsteps=25)
+    bscale = np.abs(U0[9:]).max() / min(o.dx)
+    assert np.abs(o.div_b(U0)).max() <= 1e-14 * bscale
+    assert np.abs(o.div_b(U)).max() <= 1e-13 * bscale
+    # and the cell-centred field is the face mean
+    np.testing.assert_allclose(U[5], 0.5 * (U[9] + np.roll(U[9], -1, axis=2)), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(U[7], 0.5 * (U[11] + np.roll(U[11], -1, axis=0)), rtol=0, atol=1e-15)
+
+
+def test_periodic_conservation():
+    s, V = W.orszag_tang_3d_ct((16, 12, 10))
+    o = C.Oracle(s)
+    U0 = o.prim_to_cons(V)
+    U, _, _ = o.run(U0, nsteps=25)
+    scale = np.array([np.abs(U0[q]).sum() for q in range(9)]) * o.cell_volume
+    for v0 in (1, 5):
+        scale[v0:v0 + 3] = scale[v0:v0 + 3].sum()
+    rel = np.abs(o.sums(U) - o.sums(U0))[:8] / scale[:8]
+    assert rel.max() <= 1e-13, rel
+    # the face field's mean per axis (the mean field) is exact
+    for d in range(3):
+        assert abs(U[9 + d].mean() - U0[9 + d].mean()) <= 1e-15
+
+
+@pytest.mark.parametrize("time_order", [2, 3])
+def test_uniform_state_is_a_fixed_point(time_order):
+    s, V = W.uniform((6, 5, 4), ndim=3)
+    s.update(ct=True, glm=False, limiter="wenoz", time_order=time_order)
+    W12 = np.zeros((12,) + V.shape[1:])
+    W12[:9] = V
+    W12[8] = 0.0
+    W12[9:] = V[5:8]
+    o = C.Oracle(s)
+    U0 = o.prim_to_cons(W12)
+    U, _, _ = o.run(U0, nsteps=30)
+    if time_order == 2:
+        np.testing.assert_array_equal(U, U0)
+    else:
+        np.testing.assert_allclose(U, U0, rtol=1e-14, atol=0)
+
+
+def test_orszag_tang_half_turn_symmetry():
+    s, V = W.orszag_tang_3d_ct((16, 16, 8))
+    o = C.Oracle(s)
+    U, _, _ = o.run(o.prim_to_cons(V), nsteps=20)
+    R = U[:, :, ::-1, ::-1].copy()
+    for q in (1, 2, 5, 6):
+        R[q] *= -1
+    # faces sit half a cell below their cell: the mirror of lower face i is
+    # lower face n - i
+    R[9] = -np.roll(U[9][:, ::-1, ::-1], 1, axis=2)
+    R[10] = -np.roll(U[10][:, ::-1, ::-1], 1, axis=1)
+    R[11] = U[11][:, ::-1, ::-1]
+    scale = np.abs(U).max(axis=(1, 2, 3), keepdims=True) + 1e-300
+    assert (np.abs(U - R) / scale)[:8].max() <= 1e-12
+    assert (np.abs(U - R) / np.abs(U[9:]).max())[9:].max() <= 1e-12
+
+
+def test_cpa_3d_second_order():
+    def err(n):
+        s, V = W.cpa_wave_3d_ct(n)
+        o = C.Oracle(s)
+        U, _, _ = o.run(o.prim_to_cons(V), t_end=s["period"])
+        Vf = o.cons_to_prim(U)
+        comps = [1, 2, 3, 5, 6, 7]
+        return np.mean(np.abs(Vf[comps] - V[comps]))
+
+    e8, e16 = err(8), err(16)
+    assert math.log2(e8 / e16) >= 1.8, (e8, e16)
+    assert e16 <= 8e-3, e16
+
+
+def test_config_checks():
+    s, _ = W.orszag_tang((8, 8))
+    s.update(ct=True, glm=False)
+    with pytest.raises(C.OracleError):
+        C.Oracle(s).cfl(np.ones((12, 1, 8, 8)))  # 2D is refused
+    s, V = W.orszag_tang_3d_ct(8)
+    s["glm"] = True
+    with pytest.raises(C.OracleError):
+        C.Oracle(s).prim_to_cons(V)  # GLM and CT together are refused
