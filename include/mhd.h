@@ -24,21 +24,31 @@
  *   - time: SSP-RK2 or SSP-RK3 (Shu & Osher 1988; RK3 is the benchmark
  *     integrator of the paper), dt and c_h fixed for the step;
  *   - CFL: dt = C / max_{cells,d} (|v_d| + c_f,d)/dx_d and
- *     c_h = max_{cells,d} (|v_d| + c_f,d), reduced in FP64.
+ *     c_h = max_{cells,d} (|v_d| + c_f,d), reduced in FP64;
+ *   - divergence control by constrained transport instead of GLM (the
+ *     paper's weak-scaling runs; Evans & Hawley 1988) when ct = 1: the
+ *     field lives on the cell faces, each face's value is the normal field
+ *     of its Riemann problem, edge EMFs are the arithmetic mean of the four
+ *     face fluxes around the edge (Balsara & Spicer 1999), faces advance by
+ *     the discrete curl of the EMFs with each Runge-Kutta stage, and the
+ *     cell field is the mean of each cell's two faces along each axis.
  * Magnetic pressure is |B|^2/2; ideal gas E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2
  * (psi is not part of E).  No density or pressure floors: a non-physical
  * state is reported as MHD_ERR_NONPHYSICAL.
  *
  * Layout: every state array is one contiguous device buffer of shape
- * [9][nz][ny][nx] (x fastest), interior cells only, element type of the
+ * [9][nz][ny][nx] (x fastest), interior cells only; with constrained
+ * transport [12][nz][ny][nx], components 9..11 the face field bx, by, bz on
+ * each cell's lower x, y, z face and 5..7 the cell field (face means),
+ * maintained by the library.  Element type of the
  * context (float for MHD_F32, double for MHD_F64), at least 16-byte
  * aligned.  Adjoint arrays (lambda) are always double with the same shape.
  * Inactive dimensions have n = 1.
  *
  * Ownership: the caller owns every state, adjoint and primitive buffer.
  * The library owns the context and its scratch (stage-1 buffer when the
- * caller passes none, the SSP-RK3 stage-2 buffer, reduction partials,
- * result and error words), all
+ * caller passes none, the SSP-RK3 stage-2 buffer, the constrained-transport
+ * flux and EMF buffers, reduction partials, result and error words), all
  * allocated by mhd_init and freed by mhd_destroy; mhd_step,
  * mhd_step_adjoint and mhd_cfl_dt allocate nothing.
  *
@@ -79,8 +89,9 @@ enum { MHD_MINMOD = 0, MHD_MC = 1, MHD_WENOZ = 2 }; /* reconstruction */
 enum { MHD_PERIODIC = 0, MHD_OUTFLOW = 1 }; /* boundary per face        */
 /* MHD_FLAG_ADJOINT: mhd_init also allocates the adjoint scratch (an FP64
  * stage cotangent, 9 doubles per cell); mhd_step_adjoint needs it.  The
- * adjoint covers the PLM reconstructions with SSP-RK2 only: with WENO-Z or
- * SSP-RK3 mhd_init returns MHD_ERR_UNSUPPORTED for this flag. */
+ * adjoint covers the PLM reconstructions with SSP-RK2 and cell-centred B
+ * only: with WENO-Z, SSP-RK3 or constrained transport mhd_init returns
+ * MHD_ERR_UNSUPPORTED for this flag. */
 enum { MHD_FLAG_ADJOINT = 1 };
 
 typedef struct {
@@ -98,16 +109,18 @@ typedef struct {
     double cfl;        /* Courant number C in (0, 1]                         */
     double glm_alpha;  /* GLM damping parameter alpha >= 0                   */
     int32_t time_order; /* 2: SSP-RK2, 3: SSP-RK3                            */
-    int32_t reserved;  /* must be 0                                          */
+    int32_t ct;        /* 1: constrained transport (3D, periodic, glm = 0)   */
 } mhd_config;
 
 /* Create a context for one grid on the current HIP device.  hip_stream is a
  * hipStream_t (NULL = the null stream).  Allocates the library scratch.
  * Returns MHD_ERR_ARG for an invalid config (bad ndim, n, bounds, dtype,
- * solver, limiter, time_order, reserved != 0, mixed periodic/outflow on one
- * axis, gamma <= 1, cfl not in (0,1], glm_alpha < 0), MHD_ERR_UNSUPPORTED
- * for MHD_FLAG_ADJOINT with WENO-Z or SSP-RK3, MHD_ERR_NO_DEVICE when no
- * gfx950 device is current.  *out is NULL on failure. */
+ * solver, limiter, time_order, ct not 0 or 1, ct with glm = 1, mixed
+ * periodic/outflow on one axis, gamma <= 1, cfl not in (0,1],
+ * glm_alpha < 0), MHD_ERR_UNSUPPORTED for MHD_FLAG_ADJOINT with WENO-Z,
+ * SSP-RK3 or ct = 1 and for ct = 1 on a grid that is not 3D and periodic,
+ * MHD_ERR_NO_DEVICE when no gfx950 device is current.  *out is NULL on
+ * failure. */
 mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out);
 
 /* Release the context and its scratch (syncs).  NULL is ignored. */
@@ -119,7 +132,10 @@ mhd_status mhd_set_stream(mhd_ctx *ctx, void *hip_stream);
 /* Primitive -> conserved map (async).  V: device double [9][nz][ny][nx]
  * holding (rho, vx, vy, vz, p, Bx, By, Bz, psi); U: device state of the
  * context dtype.  E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2, computed in FP64
- * and rounded once to the state type. */
+ * and rounded once to the state type.  With constrained transport V is
+ * [12][nz][ny][nx] with the face field in 9..11 (its discrete divergence
+ * is the caller's to make zero); the cell field of U, and the B in E, are
+ * the face means, whatever V holds in 5..7. */
 mhd_status mhd_prim_to_cons(mhd_ctx *ctx, const double *V, void *U);
 
 /* CFL reduction of a state (syncs): out[0] = C / max (|v_d|+c_f,d)/dx_d

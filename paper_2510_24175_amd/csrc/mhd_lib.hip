@@ -12,6 +12,7 @@
 
 #include "../../include/mhd.h"
 #include "mhd_adjoint.hpp"
+#include "mhd_ct.hpp"
 #include "mhd_reduce.hpp"
 #include "mhd_stage.hpp"
 
@@ -24,8 +25,11 @@ struct mhd_ctx {
     long long n[3] = {1, 1, 1};
     long long ncell = 0;
     size_t elem = 4;             // bytes per state element
+    int ns = NQ;                 // state components (12 with constrained transport)
     void *u1_scratch = nullptr;  // stage-1 state when the caller passes none
     void *u2_scratch = nullptr;  // SSP-RK3 stage-2 state
+    void *ct_flx = nullptr;      // constrained transport: [6] transverse field fluxes
+    void *ct_emf = nullptr;      // constrained transport: [3] edge EMFs
     double *part = nullptr;      // NPART x part_cap block partials
     int part_cap = 0;
     double *result = nullptr;    // device NPART doubles
@@ -178,12 +182,107 @@ mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, do
     return MHD_OK;
 }
 
+// Constrained transport step (3D, periodic): per stage the stage kernel
+// (fluxes with the faces' normal field, transverse field fluxes to scratch,
+// cell update of rho, m, E), the edge EMFs, and the face update with the cell
+// field; the last face update reduces the CFL maxima and sums.
+template <typename T, int SOLVER, int LIM>
+mhd_status launch_step_ct(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, double ch, double damp)
+{
+    constexpr int TY = tile_rows<T, LIM, 3>();
+    const bool rk3 = ctx->cfg.time_order == 3;
+    const Launch L = plan_stage(ctx, TY);
+    StageArgs<T> a;
+    a.part = ctx->part;
+    a.flag = ctx->flag;
+    a.flx = (T *)ctx->ct_flx;
+    a.nx = (int)ctx->n[0];
+    a.ny = (int)ctx->n[1];
+    a.nz = (int)ctx->n[2];
+    a.nxy = ctx->n[0] * ctx->n[1];
+    a.ncell = ctx->ncell;
+    for (int d = 0; d < 3; ++d) {
+        a.per[d] = 1;
+        a.idx[d] = (T)(1.0 / ctx->dx[d]);
+        a.idx_d[d] = 1.0 / ctx->dx[d];
+    }
+    a.kz = L.kz;
+    a.tiles_x = L.tiles_x;
+    a.tiles_y = L.tiles_y;
+    a.chunks = L.chunks;
+    a.nblocks = L.nblocks;
+    a.dt = (T)dt;
+    a.damp = (T)damp;
+    a.gamma_d = ctx->cfg.gamma;
+    a.ph = make_phys<T>(ctx, ch);
+    CTArgs<T> c;
+    c.un = un;
+    c.flx = (const T *)ctx->ct_flx;
+    c.emf = (T *)ctx->ct_emf;
+    c.part = ctx->part;
+    c.flag = ctx->flag;
+    c.nx = a.nx;
+    c.ny = a.ny;
+    c.nz = a.nz;
+    c.ncell = ctx->ncell;
+    c.dt = (T)dt;
+    for (int d = 0; d < 3; ++d) {
+        c.idx[d] = a.idx[d];
+        c.idx_d[d] = a.idx_d[d];
+    }
+    c.gamma_d = ctx->cfg.gamma;
+    const int nb = (int)std::min<long long>((ctx->ncell + RED_THREADS - 1) / RED_THREADS, CFL_MAX_BLOCKS);
+    c.nblocks = nb;
+
+    hipEvent_t *ev = nullptr;
+    if (ctx->timed_steps < ctx->timed_cap) ev = &ctx->events[4 * ctx->timed_steps++];
+    if (ev) HIP_TRY(ctx, hipEventRecord(ev[0], ctx->stream));
+    // one stage: uin -> uout with stage kind KIND
+    auto stage = [&](auto kind, const T *uin, T *uout) -> mhd_status {
+        constexpr int KIND = decltype(kind)::value;
+        a.uin = uin;
+        a.un = un;
+        a.uout = uout;
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, 3, KIND, TY, true>), dim3(L.nblocks), dim3(TX * TY), 0,
+                           ctx->stream, a);
+        HIP_TRY(ctx, hipGetLastError());
+        c.uin = uin;
+        c.uout = uout;
+        hipLaunchKernelGGL(ct_emf_kernel<T>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, c);
+        HIP_TRY(ctx, hipGetLastError());
+        hipLaunchKernelGGL((ct_face_kernel<T, KIND, last_stage(KIND)>), dim3(nb), dim3(RED_THREADS), 0,
+                           ctx->stream, c);
+        HIP_TRY(ctx, hipGetLastError());
+        return MHD_OK;
+    };
+    mhd_status st = stage(std::integral_constant<int, 1>{}, un, u1);
+    if (st != MHD_OK) return st;
+    if (rk3) {
+        T *u2 = (T *)ctx->u2_scratch;
+        st = stage(std::integral_constant<int, 3>{}, u1, u2);
+        if (st != MHD_OK) return st;
+        if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
+        st = stage(std::integral_constant<int, 4>{}, u2, unext);
+    } else {
+        if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
+        st = stage(std::integral_constant<int, 2>{}, u1, unext);
+    }
+    if (st != MHD_OK) return st;
+    if (ev) HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
+    hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(RED_THREADS), 0, ctx->stream,
+                       (const double *)ctx->part, nb, ctx->result);
+    HIP_TRY(ctx, hipGetLastError());
+    if (ev) HIP_TRY(ctx, hipEventRecord(ev[3], ctx->stream));
+    return MHD_OK;
+}
+
 template <typename T, int SOLVER, int LIM>
 mhd_status launch_step_nd(mhd_ctx *ctx, const void *un, void *unext, void *u1, double dt, double ch,
                           double damp)
 {
     const T *a = (const T *)un;
     T *b = (T *)unext, *c = (T *)u1;
+    if (ctx->cfg.ct) return launch_step_ct<T, SOLVER, LIM>(ctx, a, b, c, dt, ch, damp);
     switch (ctx->cfg.ndim) {
     case 1: return launch_step<T, SOLVER, LIM, 1>(ctx, a, b, c, dt, ch, damp);
     case 2: return launch_step<T, SOLVER, LIM, 2>(ctx, a, b, c, dt, ch, damp);
@@ -374,7 +473,7 @@ mhd_status check_config(const mhd_config *c, std::string &why)
     if (c->limiter != MHD_MINMOD && c->limiter != MHD_MC && c->limiter != MHD_WENOZ)
         return why = "bad limiter", MHD_ERR_ARG;
     if (c->time_order != 2 && c->time_order != 3) return why = "time_order must be 2 or 3", MHD_ERR_ARG;
-    if (c->reserved != 0) return why = "reserved must be 0", MHD_ERR_ARG;
+    if (c->ct != 0 && c->ct != 1) return why = "ct must be 0 or 1", MHD_ERR_ARG;
     if (c->glm != 0 && c->glm != 1) return why = "glm must be 0 or 1", MHD_ERR_ARG;
     if ((c->flags & ~MHD_FLAG_ADJOINT) != 0) return why = "unknown flag bits", MHD_ERR_ARG;
     long long cells = 1;
@@ -399,8 +498,15 @@ mhd_status check_config(const mhd_config *c, std::string &why)
     if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return why = "cfl must be in (0, 1]", MHD_ERR_ARG;
     if (!(c->glm_alpha >= 0.0) || !std::isfinite(c->glm_alpha))
         return why = "glm_alpha must be >= 0", MHD_ERR_ARG;
-    if ((c->flags & MHD_FLAG_ADJOINT) && (c->limiter == MHD_WENOZ || c->time_order != 2))
-        return why = "the adjoint covers PLM with SSP-RK2 only", MHD_ERR_UNSUPPORTED;
+    if ((c->flags & MHD_FLAG_ADJOINT) && (c->limiter == MHD_WENOZ || c->time_order != 2 || c->ct))
+        return why = "the adjoint covers PLM with SSP-RK2 and GLM only", MHD_ERR_UNSUPPORTED;
+    if (c->ct) {
+        if (c->glm) return why = "constrained transport replaces GLM (glm must be 0)", MHD_ERR_ARG;
+        if (c->ndim != 3) return why = "constrained transport is three-dimensional", MHD_ERR_UNSUPPORTED;
+        for (int d = 0; d < 3; ++d)
+            if (c->bc[d][0] != MHD_PERIODIC)
+                return why = "constrained transport needs periodic axes", MHD_ERR_UNSUPPORTED;
+    }
     return MHD_OK;
 }
 
@@ -416,6 +522,8 @@ void free_ctx(mhd_ctx *ctx)
     destroy_events(ctx);
     if (ctx->u1_scratch) (void)hipFree(ctx->u1_scratch);
     if (ctx->u2_scratch) (void)hipFree(ctx->u2_scratch);
+    if (ctx->ct_flx) (void)hipFree(ctx->ct_flx);
+    if (ctx->ct_emf) (void)hipFree(ctx->ct_emf);
     if (ctx->part) (void)hipFree(ctx->part);
     if (ctx->result) (void)hipFree(ctx->result);
     if (ctx->flag) (void)hipFree(ctx->flag);
@@ -518,9 +626,12 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
                                           : tile_rows<double, LIM_MINMOD, 3>());
     const Launch L = plan_stage(ctx, ty);
     ctx->part_cap = std::max(L.nblocks, CFL_MAX_BLOCKS);
-    hipError_t e = hipMalloc(&ctx->u1_scratch, (size_t)NQ * ctx->ncell * ctx->elem);
+    ctx->ns = cfg->ct ? 12 : NQ;
+    hipError_t e = hipMalloc(&ctx->u1_scratch, (size_t)ctx->ns * ctx->ncell * ctx->elem);
     if (e == hipSuccess && cfg->time_order == 3)
-        e = hipMalloc(&ctx->u2_scratch, (size_t)NQ * ctx->ncell * ctx->elem);
+        e = hipMalloc(&ctx->u2_scratch, (size_t)ctx->ns * ctx->ncell * ctx->elem);
+    if (e == hipSuccess && cfg->ct) e = hipMalloc(&ctx->ct_flx, (size_t)6 * ctx->ncell * ctx->elem);
+    if (e == hipSuccess && cfg->ct) e = hipMalloc(&ctx->ct_emf, (size_t)3 * ctx->ncell * ctx->elem);
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->part, (size_t)NPART * ctx->part_cap * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->result, NPART * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->flag, sizeof(int));
@@ -557,7 +668,14 @@ mhd_status mhd_prim_to_cons(mhd_ctx *ctx, const double *V, void *U)
     if (!V || !U) return fail(ctx, MHD_ERR_ARG, "null buffer");
     const int nb = (int)std::min<long long>((ctx->ncell + RED_THREADS - 1) / RED_THREADS, 8192);
     const double ig = 1.0 / (ctx->cfg.gamma - 1.0);
-    if (ctx->cfg.dtype == MHD_F32)
+    const int nx = (int)ctx->n[0], ny = (int)ctx->n[1], nz = (int)ctx->n[2];
+    if (ctx->cfg.ct && ctx->cfg.dtype == MHD_F32)
+        hipLaunchKernelGGL(prim_to_cons_ct_kernel<float>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, V,
+                           (float *)U, nx, ny, nz, ig);
+    else if (ctx->cfg.ct)
+        hipLaunchKernelGGL(prim_to_cons_ct_kernel<double>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, V,
+                           (double *)U, nx, ny, nz, ig);
+    else if (ctx->cfg.dtype == MHD_F32)
         hipLaunchKernelGGL(prim_to_cons_kernel<float>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, V,
                            (float *)U, ctx->ncell, ig);
     else

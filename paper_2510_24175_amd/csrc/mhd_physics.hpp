@@ -368,15 +368,21 @@ template <typename T> __device__ __forceinline__ T pick3(int d, T a0, T a1, T a2
 
 // Interface flux from two unrotated primitive face states along axis d:
 // GLM (B_n, psi) interface solve, MHD solver on the 8 MHD components with
-// B_n replaced by B_n*, then F(B_n) = psi*, F(psi) = c_h^2 B_n*.
-template <typename T, int SOLVER>
-__device__ __forceinline__ void face_flux(const T *VL, const T *VR, int d, const Phys<T> &ph, T *F)
+// B_n replaced by B_n*, then F(B_n) = psi*, F(psi) = c_h^2 B_n*.  With
+// constrained transport (CT) the normal field is the face's own value bnf
+// and F(B_n) = F(psi) = 0.
+template <typename T, int SOLVER, bool CT = false>
+__device__ __forceinline__ void face_flux(const T *VL, const T *VR, int d, const Phys<T> &ph, T *F,
+                                          T bnf = T(0))
 {
     // frame (n, t1, t2) = (d, d+1, d+2) mod 3
     const T bnL = pick3(d, VL[BX], VL[BY], VL[BZ]);
     const T bnR = pick3(d, VR[BX], VR[BY], VR[BZ]);
     T bns, psis;
-    if (ph.glm) {
+    if (CT) {
+        bns = bnf;
+        psis = T(0);
+    } else if (ph.glm) {
         bns = T(0.5) * (bnL + bnR) - (VR[PSI] - VL[PSI]) * ph.half_ich;
         psis = T(0.5) * (VL[PSI] + VR[PSI]) - T(0.5) * ph.ch * (bnR - bnL);
     } else {
@@ -407,7 +413,7 @@ __device__ __forceinline__ void face_flux(const T *VL, const T *VR, int d, const
         hlld_flux(L, R, ph, f);
     else
         hll_flux(L, R, ph, f);
-    const T fbn = ph.glm ? psis : T(0);
+    const T fbn = (!CT && ph.glm) ? psis : T(0);
     F[RHO] = f[0];
     F[ENG] = f[4];
     // unrotate: component x is (n, t2, t1) for d = (0, 1, 2), etc.
@@ -417,7 +423,7 @@ __device__ __forceinline__ void face_flux(const T *VL, const T *VR, int d, const
     F[BX] = pick3(d, fbn, f[7], f[6]);
     F[BY] = pick3(d, f[6], fbn, f[7]);
     F[BZ] = pick3(d, f[7], f[6], fbn);
-    F[PSI] = ph.glm ? ph.ch2 * bns : T(0);
+    F[PSI] = (!CT && ph.glm) ? ph.ch2 * bns : T(0);
 }
 
 // Boundary index map of a ghost or interior coordinate m on an axis of n >= 2

@@ -38,7 +38,12 @@ constexpr int TX = 64;
 constexpr int NPART = 11;
 
 template <typename T> struct StageArgs {
-    const T *uin;   // state the fluxes are built from (Un or U1)
+    const T *uin;   // state the fluxes are built from (Un or U1); with
+                    // constrained transport its components 9..11 are the
+                    // face field on each cell's lower x, y, z face
+    T *flx;         // constrained transport: [6][ncell] transverse field
+                    // fluxes of each cell's lower faces (x: By, Bz; y: Bx,
+                    // Bz; z: Bx, By)
     const T *un;    // Un (later stages' combine); equals uin in stage 1
     T *uout;        // this stage's output (U1, U2 or U_next)
     double *part;   // last stage: NPART x nblocks partials
@@ -165,11 +170,14 @@ template <typename T, int LIM> constexpr int stage_min_waves()
 // psi and reduces the CFL maxima and the conservation sums.
 constexpr bool last_stage(int kind) { return kind == 2 || kind == 4; }
 
-template <typename T, int SOLVER, int LIM, int NDIM, int KIND, int TY>
+template <typename T, int SOLVER, int LIM, int NDIM, int KIND, int TY, bool CT = false>
 __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_kernel(const StageArgs<T> a)
 {
     constexpr bool WENO = LIM == LIM_WENOZ;
-    constexpr bool LAST = last_stage(KIND);
+    // with constrained transport the cell field is final only after the
+    // face update, which therefore takes the last stage's reductions
+    constexpr bool LAST = last_stage(KIND) && !CT;
+    static_assert(!CT || NDIM == 3, "constrained transport is three-dimensional");
     constexpr int H = WENO ? 3 : 2;        // stencil half width (ghost layers)
     constexpr int NT = TX * TY;
     constexpr int HY = NDIM >= 2 ? H : 0;  // y halo width in LDS
@@ -276,19 +284,37 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
     };
 
     // Flux through one face of the plane from its two states, stored (dst
-    // may be null for padding items).
-    auto flux_item = [&](auto dir, const T *VL, const T *VR, T *dst, int fstride) {
+    // may be null for padding items).  Constrained transport: fc is the cell
+    // whose lower face this is (its face value is the normal field) and, for
+    // the tile's own faces (mine), the two transverse field fluxes go to flx.
+    auto flux_item = [&](auto dir, const T *VL, const T *VR, T *dst, int fstride, long long fc,
+                         bool mine) {
         constexpr int D = decltype(dir)::value;
         T F[NQ];
-        face_flux<T, SOLVER>(VL, VR, D, a.ph, F);
+        if constexpr (CT) {
+            face_flux<T, SOLVER, true>(VL, VR, D, a.ph, F, a.uin[(9 + D) * a.ncell + fc]);
+            if (mine) {
+                a.flx[(2 * D) * a.ncell + fc] = F[D == 0 ? BY : BX];
+                a.flx[(2 * D + 1) * a.ncell + fc] = F[BZ];
+            }
+        } else {
+            face_flux<T, SOLVER>(VL, VR, D, a.ph, F);
+        }
         if (dst) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) dst[q * fstride] = F[q];
         }
     };
+    // owner cell (in plane zk) of the lower face of tile cell (x, y), and
+    // whether that cell is in the grid
+    auto face_cell = [&](long long zk, int x, int y) -> long long {
+        return zk + (long long)remap_index(j0 + y, a.ny, a.per[1]) * a.nx + remap_index(i0 + x, a.nx, a.per[0]);
+    };
+    auto in_grid = [&](int x, int y) -> bool { return (i0 + x < a.nx) & (j0 + y < a.ny); };
     // PLM face from the LDS stencil w0..w3 (stride apart; the face lies
     // between w1 and w2): limited slopes of w1 and w2, face states, flux.
-    auto face_item = [&](auto dir, const T *base, int stride, T *dst, int fstride) {
+    auto face_item = [&](auto dir, const T *base, int stride, T *dst, int fstride, long long fc,
+                         bool mine) {
         T VL[NQ], VR[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -299,7 +325,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             VL[q] = w1 + T(0.5) * s1;
             VR[q] = w2 - T(0.5) * s2;
         }
-        flux_item(dir, VL, VR, dst, fstride);
+        flux_item(dir, VL, VR, dst, fstride, fc, mine);
     };
 
     // z window.  PLM: V(k), V(k+1) and the limited slope of V(k).  WENO-Z:
@@ -338,7 +364,10 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
                 VR[q] = Wz[0][q] - T(0.5) * D0[q];
             }
         }
-        face_flux<T, SOLVER>(VL, VR, 2, a.ph, Fzm);
+        if constexpr (CT)
+            face_flux<T, SOLVER, true>(VL, VR, 2, a.ph, Fzm, a.uin[11 * a.ncell + zoff(k0) + own]);
+        else
+            face_flux<T, SOLVER>(VL, VR, 2, a.ph, Fzm);
     } else {
         prim_at(own, Wz[ZC]);
     }
@@ -389,7 +418,10 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
                     VR[q] = Wz[1][q] - T(0.5) * D1[q];
                 }
             }
-            face_flux<T, SOLVER>(VL, VR, 2, a.ph, Fzp);
+            if constexpr (CT)
+                face_flux<T, SOLVER, true>(VL, VR, 2, a.ph, Fzp, a.uin[11 * a.ncell + zoff(k + 1) + own]);
+            else
+                face_flux<T, SOLVER>(VL, VR, 2, a.ph, Fzp);
             // slide the window by one plane
 #pragma unroll
             for (int m = 0; m + 1 < ZW; ++m) {
@@ -455,7 +487,8 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
                         VR[q] = EX[NQ * QS + q * QS + r * NXE + f + 1];
                     }
                     flux_item(std::integral_constant<int, 0>{}, VL, VR,
-                              valid ? &FXs[r * (TX + 1) + f] : nullptr, TY * (TX + 1));
+                              valid ? &FXs[r * (TX + 1) + f] : nullptr, TY * (TX + 1), face_cell(zk, f, r),
+                              valid && f < TX && in_grid(f, r));
                 } else {
                     const int it = (ch - NCHX) * TX + tx;
                     const int r = it / TX, c = it - r * TX;
@@ -465,7 +498,8 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
                         VL[q] = EY[q * QS + r * TX + c];
                         VR[q] = EY[NQ * QS + q * QS + (r + 1) * TX + c];
                     }
-                    flux_item(std::integral_constant<int, 1>{}, VL, VR, &FYs[r * TX + c], (TY + 1) * TX);
+                    flux_item(std::integral_constant<int, 1>{}, VL, VR, &FYs[r * TX + c], (TY + 1) * TX,
+                              face_cell(zk, c, r), r < TY && in_grid(c, r));
                 }
             }
         } else {
@@ -481,13 +515,14 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
                     const int f = valid ? it - r * (TX + 1) : 0;
                     // cells f-2 .. f+1 of row r
                     face_item(std::integral_constant<int, 0>{}, &P[(r + HY) * PX + f], 1,
-                              valid ? &FXs[r * (TX + 1) + f] : nullptr, TY * (TX + 1));
+                              valid ? &FXs[r * (TX + 1) + f] : nullptr, TY * (TX + 1), face_cell(zk, f, r),
+                              valid && f < TX && in_grid(f, r));
                 } else {
                     const int it = (ch - NCHX) * TX + tx;
                     const int r = it / TX, c = it - r * TX;
                     // rows r-2 .. r+1 of column c
                     face_item(std::integral_constant<int, 1>{}, &P[r * PX + c + H], PX, &FYs[r * TX + c],
-                              (TY + 1) * TX);
+                              (TY + 1) * TX, face_cell(zk, c, r), r < TY && in_grid(c, r));
                 }
             }
         }
@@ -527,8 +562,16 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             }
             if (LAST) out[PSI] *= a.damp;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q)
+            for (int q = 0; q < NQ; ++q) {
+                // constrained transport: the face update writes the cell field
+                if (CT && q >= BX && q <= BZ) continue;
                 __builtin_nontemporal_store(out[q], &a.uout[q * a.ncell + c]);  // not read again here
+            }
+            if constexpr (CT) {
+                // transverse field fluxes of this cell's lower z face
+                a.flx[4 * a.ncell + c] = Fzm[BX];
+                a.flx[5 * a.ncell + c] = Fzm[BY];
+            }
             if (LAST) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) sum[q] += (double)out[q];

@@ -50,7 +50,7 @@ class mhd_config(ctypes.Structure):
         ("cfl", ctypes.c_double),
         ("glm_alpha", ctypes.c_double),
         ("time_order", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("ct", ctypes.c_int32),
     ]
 
 
@@ -114,7 +114,7 @@ def make_config(setup, dtype="f32", adjoint=False):
     c.cfl = float(setup["cfl"])
     c.glm_alpha = float(setup.get("glm_alpha", 0.1))
     c.time_order = int(setup.get("time_order", 2))
-    c.reserved = 0
+    c.ct = 1 if setup.get("ct", False) else 0
     return c
 
 
@@ -138,7 +138,9 @@ class Context:
         self.tdtype = TORCH_DTYPE[dtype]
         self.adjoint = adjoint
         self.cfg = make_config(setup, dtype, adjoint)
-        self.shape = (9, int(setup["n"][2]), int(setup["n"][1]), int(setup["n"][0]))
+        # constrained transport: three more components, the face field
+        self.nstate = 12 if setup.get("ct", False) else 9
+        self.shape = (self.nstate, int(setup["n"][2]), int(setup["n"][1]), int(setup["n"][0]))
         ndim = int(setup["ndim"])
         dx = [(setup["hi"][d] - setup["lo"][d]) / setup["n"][d] for d in range(3)]
         self.dh_min = min(dx[d] for d in range(ndim))

@@ -49,7 +49,7 @@ def _base():
 @pytest.mark.parametrize("field,value", [
     ("ndim", 0), ("ndim", 4), ("dtype", 7), ("riemann", 3), ("limiter", 9), ("glm", 2),
     ("flags", 2), ("gamma", 1.0), ("cfl", 0.0), ("cfl", 1.5), ("glm_alpha", -0.1),
-    ("limiter", 3), ("time_order", 1), ("time_order", 4), ("reserved", 1),
+    ("limiter", 3), ("time_order", 1), ("time_order", 4), ("ct", 2),
 ])
 def test_invalid_config_is_rejected_before_device_use(field, value):
     cfg = _base()
@@ -62,7 +62,24 @@ def test_config_layout_matches_the_header():
     # (sizes of the C struct on x86-64 / LP64)
     assert ctypes.sizeof(mhd.mhd_config) == 152
     assert mhd.mhd_config.time_order.offset == 144
-    assert mhd.mhd_config.reserved.offset == 148
+    assert mhd.mhd_config.ct.offset == 148
+
+
+def test_constrained_transport_config_checks():
+    s, _ = W.orszag_tang_3d_ct(8)
+    cfg = mhd.make_config(s, "f32")
+    assert cfg.ct == 1 and cfg.glm == 0
+    cfg.glm = 1
+    assert _init(cfg) == mhd.MHD_ERR_ARG  # CT replaces GLM
+    cfg = mhd.make_config(s, "f32", adjoint=True)
+    assert _init(cfg) == mhd.MHD_ERR_UNSUPPORTED
+    cfg = mhd.make_config(s, "f32")
+    cfg.bc[2][0] = cfg.bc[2][1] = mhd.MHD_OUTFLOW
+    assert _init(cfg) == mhd.MHD_ERR_UNSUPPORTED
+    s2, _ = W.orszag_tang(8)
+    cfg = mhd.make_config(s2, "f32")
+    cfg.ct, cfg.glm = 1, 0
+    assert _init(cfg) == mhd.MHD_ERR_UNSUPPORTED  # 2D
 
 
 @pytest.mark.parametrize("limiter,time_order", [("wenoz", 2), ("wenoz", 3), ("minmod", 3)])

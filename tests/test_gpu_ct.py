@@ -1,0 +1,154 @@
+"""GPU constrained transport against the FP64 CPU oracle, through the C ABI.
+
+Bars as for the other parity tests: relative L1 per component (the 9 cell
+components and the 3 face components) <= 1e-10 with FP64 state and <= 1e-5
+with FP32 state.  The face divergence of the GPU states stays at rounding
+(FP64) or at FP32 rounding accumulated over the run; periodic sums are
+conserved.  Shapes are ragged (partial x and y tiles, a partial z chunk).
+"""
+import numpy as np
+import pytest
+
+from oracle import coracle as C
+from paper_2510_24175_amd import workloads as W
+from tests.helpers import rel_l1
+from tests.test_gpu_parity import _say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return torch
+
+
+def _faces_rel_l1(A, B):
+    return np.array([np.abs(A[q] - B[q]).sum() / np.abs(B[9:]).sum() for q in (9, 10, 11)])
+
+
+def _run_both(torch, s, V, dtype, nsteps):
+    from paper_2510_24175_amd.mhd import Context
+    from paper_2510_24175_amd.rollout import advance
+    ctx = Context(s, dtype)
+    U0 = ctx.prim_to_cons(torch.from_numpy(V).cuda())
+    U, _, hg = advance(ctx, U0, nsteps=nsteps)
+    torch.cuda.synchronize()
+    o = C.Oracle(s)
+    Uo, _, ho = o.run(o.prim_to_cons(V), nsteps=nsteps)
+    return ctx, o, U.double().cpu().numpy(), Uo, hg, ho
+
+
+def _check(torch, name, s, V, dtype, nsteps):
+    _say(f"[gpu-ct] {name} dtype={dtype} n={s['n']} steps={nsteps} {s['limiter']} rk{s['time_order']}")
+    ctx, o, Ug, Uo, hg, ho = _run_both(torch, s, V, dtype, nsteps)
+    err = rel_l1(Ug[:9], Uo[:9])
+    errf = _faces_rel_l1(Ug, Uo)
+    _say(f"    rel L1 cell {np.array2string(err[:8], precision=2)} faces {np.array2string(errf, precision=2)}")
+    assert max(err[:8].max(), errf.max()) <= TOL[dtype], (err, errf)
+    dg, do = np.array([h[0] for h in hg]), np.array([h[0] for h in ho])
+    assert (np.abs(dg - do) / do.max()).max() <= (1e-12 if dtype == "f64" else 1e-5)
+    div = np.abs(o.div_b(Ug)).max() * min(o.dx) / np.abs(Ug[9:]).max()
+    _say(f"    face divergence (relative to |B|/dx): {div:.2e}")
+    assert div <= (1e-13 if dtype == "f64" else 1e-5)
+    return ctx, o, Ug, Uo
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("limiter,time_order", [("wenoz", 3), ("minmod", 2)])
+def test_orszag_tang_3d_ct(torch_cuda, dtype, limiter, time_order):
+    s, V = W.orszag_tang_3d_ct((70, 37, 19))
+    s["limiter"], s["time_order"] = limiter, time_order
+    _check(torch_cuda, "orszag_tang_3d_ct", s, V, dtype, 20)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("riemann", ["hlld", "hll"])
+def test_cpa_3d_ct(torch_cuda, dtype, riemann):
+    s, V = W.cpa_wave_3d_ct((34, 30, 36), riemann=riemann)
+    _check(torch_cuda, "cpa_3d_ct", s, V, dtype, 15)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ct_sums_and_cfl(torch_cuda, dtype):
+    # the reductions of the last face update against the oracle's
+    torch = torch_cuda
+    from paper_2510_24175_amd.mhd import Context
+    s, V = W.orszag_tang_3d_ct((40, 36, 20))
+    ctx = Context(s, dtype)
+    o = C.Oracle(s)
+    Uo = o.prim_to_cons(V)
+    Ug = ctx.prim_to_cons(torch.from_numpy(V).cuda())
+    dt, ch = o.cfl(Uo)
+    dtg, chg = ctx.cfl_dt(Ug)
+    tol = 1e-13 if dtype == "f64" else 1e-6
+    assert abs(dtg / dt - 1) <= tol and abs(chg / ch - 1) <= tol
+    out = torch.empty_like(Ug)
+    ctx.step(Ug, out, dt, ch, 1.0)
+    dt2, ch2, sums = ctx.step_info()
+    Uo1 = o.step(Uo, dt, ch, 1.0)
+    dt2_o, ch2_o = o.cfl(Uo1)
+    tol = 1e-12 if dtype == "f64" else 1e-6
+    assert abs(dt2 / dt2_o - 1) <= tol and abs(ch2 / ch2_o - 1) <= tol
+    scale = np.array([np.abs(Uo1[q]).sum() for q in range(9)]) * o.cell_volume
+    for v0 in (1, 5):
+        scale[v0:v0 + 3] = scale[v0:v0 + 3].sum()
+    assert (np.abs(np.array(sums) - o.sums(Uo1))[:8] / scale[:8]).max() <= tol
+
+
+@pytest.mark.parametrize("time_order", [2, 3])
+def test_ct_uniform_state(torch_cuda, time_order):
+    torch = torch_cuda
+    from paper_2510_24175_amd.mhd import Context
+    from paper_2510_24175_amd.rollout import advance
+    s, V = W.uniform((70, 9, 7), ndim=3)
+    s.update(ct=True, glm=False, limiter="wenoz", time_order=time_order)
+    W12 = np.zeros((12,) + V.shape[1:])
+    W12[:9] = V
+    W12[8] = 0.0
+    W12[9:] = V[5:8]
+    _say(f"[gpu-ct] uniform rk{time_order}")
+    ctx = Context(s, "f64")
+    U0 = ctx.prim_to_cons(torch.from_numpy(W12).cuda())
+    U, _, _ = advance(ctx, U0, nsteps=30)
+    if time_order == 2:
+        assert torch.equal(U, U0)
+    else:
+        assert torch.allclose(U, U0, rtol=1e-14, atol=0.0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_orszag_tang_3d_ct_352(torch_cuda, dtype):
+    """The paper's weak-scaling configuration per GPU (704 x 704 x 352 per
+    four-GPU node = 352^3), WENO-Z + HLLD + SSP-RK3 with constrained
+    transport, in the launch configuration the bench times: two steps,
+    checked for the face divergence and the FP64 conservation sums."""
+    torch = torch_cuda
+    from paper_2510_24175_amd.mhd import Context
+    n = 352
+    _say(f"[gpu-ct] Orszag-Tang 3D CT {n}^3 {dtype}")
+    s, V = W.orszag_tang_3d_ct(n)
+    ctx = Context(s, dtype)
+    U = ctx.prim_to_cons(torch.from_numpy(V).cuda())
+    del V
+    dt, ch = ctx.cfl_dt(U)
+    out = torch.empty_like(U)
+    ctx.step(U, out, dt, ch, 1.0)
+    _, _, sums1 = ctx.step_info()
+    dt2, ch2, _ = ctx.step_info()
+    ctx.step(out, U, dt2, ch2, 1.0)
+    _, _, sums2 = ctx.step_info()
+    torch.cuda.synchronize()
+    Ug = U.double().cpu().numpy()
+    o = C.Oracle(s)
+    div = np.abs(o.div_b(Ug)).max() * min(o.dx) / np.abs(Ug[9:]).max()
+    scale = np.array([np.abs(Ug[q]).sum() for q in range(9)]) * o.cell_volume
+    for v0 in (1, 5):
+        scale[v0:v0 + 3] = scale[v0:v0 + 3].sum()
+    dsum = (np.abs(np.array(sums2) - np.array(sums1))[:8] / scale[:8]).max()
+    _say(f"    face divergence {div:.2e}, conservation over a step {dsum:.2e}")
+    assert div <= (1e-13 if dtype == "f64" else 1e-5)
+    assert dsum <= (1e-12 if dtype == "f64" else 1e-6)
