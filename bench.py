@@ -110,8 +110,13 @@ def run_gpu(n, dtype, steps, warmup, workload="turbulence", limiter="minmod", ti
     # algorithmic HBM traffic: the first stage reads Un and writes U1
     # (18 s B/cell), every later stage reads Un and its input stage and
     # writes its output (27 s B/cell): 45 s B/cell per SSP-RK2 step, 72 s
-    # per SSP-RK3 step
-    res["alg_bytes_step"] = (18 + 27 * (time_order - 1)) * s * ncell
+    # per SSP-RK3 step.  Constrained transport adds per stage the face field
+    # (3 components read with the input, 3 more with Un after the first
+    # stage, 3 written), the 6 transverse fluxes (written, read) and the 3
+    # EMFs (written, read): 36 s B/cell in the first stage, 39 s after.
+    ct = setup.get("ct", False)
+    res["alg_bytes_step"] = ((18 + 27 * (time_order - 1)) +
+                             ((36 + 39 * (time_order - 1)) if ct else 0)) * s * ncell
     res["alg_bytes_stage2"] = 27 * s * ncell
     res["hbm_frac_step"] = res["alg_bytes_step"] / (wall / steps) / (HBM_PEAK_GBS * 1e9)
     del a, b
@@ -205,6 +210,9 @@ def main():
     ap.add_argument("--paper-n", type=int, default=416)
     ap.add_argument("--paper-cases", default="ot3d_f64,ot3d_f32,cpa3d_f64",
                     help="comma list of paper-scheme runs (ot3d_f64, ot3d_f32, cpa3d_f64, cpa3d_f32)")
+    ap.add_argument("--no-ct", action="store_true")
+    ap.add_argument("--ct-n", type=int, default=352)
+    ap.add_argument("--ct-cases", default="f64,f32")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -303,6 +311,24 @@ def main():
                     cnt["valu_wave_insts"] * 4 / (1024 * 2.4e9 * r["stage2_ms"] * 1e-3), 4)
             print(f"# paper scheme {key} {pn}^3: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         out["paper_scheme"] = ps
+    if not args.no_ct:
+        # the paper's weak-scaling runs: the same scheme with constrained
+        # transport instead of GLM on its per-GPU share (704 x 704 x 352 per
+        # four-GPU node, 352^3), 3D Orszag-Tang vortex
+        cn = args.ct_n
+        cs = {"workload": f"3D Orszag-Tang vortex {cn}^3, WENO-Z + HLLD, constrained transport, SSP-RK3, "
+                          "CFL 0.3", "n": [cn] * 3}
+        for dt_ in [c.strip() for c in args.ct_cases.split(",") if c.strip()]:
+            r = run_gpu(cn, dt_, max(3, args.steps // 2), 2, workload="orszag_tang_3d_ct", limiter="wenoz",
+                        time_order=3)
+            cs[dt_] = {"value": round(r["mcells"], 2), "unit": "Mcell-updates/s",
+                       "ms_per_step": round(r["ms_per_step"], 4),
+                       "hbm_frac_step_algorithmic": round(r["hbm_frac_step"], 4),
+                       "stage_ms": {"first_two": round(r["stage1_ms"], 4), "last": round(r["stage2_ms"], 4),
+                                    "final_reduce": round(r["reduce_ms"], 4)}}
+            print(f"# constrained transport {dt_} {cn}^3: {r['ms_per_step']:.3f} ms/step", file=sys.stderr,
+                  flush=True)
+        out["constrained_transport"] = cs
     if not args.no_adjoint:
         # adjoint/forward time ratio at the adjoint workload (128^3 FP32)
         # and at the benchmark grid
