@@ -40,6 +40,16 @@ template <typename T> struct CTArgs {
 // periodic neighbour of a cell coordinate one step away
 __device__ __forceinline__ int ct_wrap(int m, int n) { return m < 0 ? m + n : (m >= n ? m - n : m); }
 
+// (i, j, k) of a cell index in 32-bit arithmetic (a constrained-transport
+// context holds 15 or more state-sized arrays, so ncell < 2^31 on any device)
+__device__ __forceinline__ void ct_coords(long long c, int nx, int ny, int &i, int &j, int &k)
+{
+    const unsigned cc = (unsigned)c, row = cc / (unsigned)nx;
+    i = (int)(cc - row * (unsigned)nx);
+    k = (int)(row / (unsigned)ny);
+    j = (int)(row - (unsigned)k * (unsigned)ny);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) ct_emf_kernel(const CTArgs<T> a)
 {
@@ -48,7 +58,8 @@ __global__ void __launch_bounds__(RED_THREADS) ct_emf_kernel(const CTArgs<T> a)
     const T *FyBz = a.flx + 3 * a.ncell, *FzBx = a.flx + 4 * a.ncell, *FzBy = a.flx + 5 * a.ncell;
     for (long long c = (long long)blockIdx.x * RED_THREADS + threadIdx.x; c < a.ncell;
          c += (long long)gridDim.x * RED_THREADS) {
-        const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / nxy);
+        int i, j, k;
+        ct_coords(c, a.nx, a.ny, i, j, k);
         const long long xm = c - i + ct_wrap(i - 1, a.nx);
         const long long ym = c + (long long)(ct_wrap(j - 1, a.ny) - j) * a.nx;
         const long long zm = c + (long long)(ct_wrap(k - 1, a.nz) - k) * nxy;
@@ -81,7 +92,8 @@ __global__ void __launch_bounds__(RED_THREADS) ct_face_kernel(const CTArgs<T> a)
     bool ok = true;
     for (long long c = (long long)blockIdx.x * RED_THREADS + threadIdx.x; c < nc;
          c += (long long)gridDim.x * RED_THREADS) {
-        const int i = (int)(c % a.nx), j = (int)((c / a.nx) % a.ny), k = (int)(c / nxy);
+        int i, j, k;
+        ct_coords(c, a.nx, a.ny, i, j, k);
         const long long dxp = ct_wrap(i + 1, a.nx) - i;               // +x neighbour offset
         const long long dyp = (long long)(ct_wrap(j + 1, a.ny) - j) * a.nx;
         const long long dzp = (long long)(ct_wrap(k + 1, a.nz) - k) * nxy;
@@ -148,7 +160,8 @@ prim_to_cons_ct_kernel(const double *__restrict__ V, T *__restrict__ U, int nx, 
     const long long nxy = (long long)nx * ny, nc = nxy * nz;
     for (long long c = (long long)blockIdx.x * RED_THREADS + threadIdx.x; c < nc;
          c += (long long)gridDim.x * RED_THREADS) {
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / nxy);
+        int i, j, k;
+        ct_coords(c, nx, ny, i, j, k);
         const long long up[3] = {ct_wrap(i + 1, nx) - i, (long long)(ct_wrap(j + 1, ny) - j) * nx,
                                  (long long)(ct_wrap(k + 1, nz) - k) * nxy};
         double b[3];

@@ -506,6 +506,8 @@ mhd_status check_config(const mhd_config *c, std::string &why)
         for (int d = 0; d < 3; ++d)
             if (c->bc[d][0] != MHD_PERIODIC)
                 return why = "constrained transport needs periodic axes", MHD_ERR_UNSUPPORTED;
+        if (c->n[0] * c->n[1] * c->n[2] >= (1LL << 31))
+            return why = "constrained transport needs fewer than 2^31 cells", MHD_ERR_ARG;
     }
     return MHD_OK;
 }
