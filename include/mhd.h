@@ -190,7 +190,8 @@ mhd_status mhd_step_adjoint(mhd_ctx *ctx, const void *Un, const void *U1, const 
                             double *lam_n, double dt, double c_h, double damp);
 
 /* Adjoint of mhd_prim_to_cons (async): lam_V = (dU/dV)^T lam_U, all double,
- * V the primitive state the forward map was applied to. */
+ * V the primitive state the forward map was applied to.  MHD_ERR_UNSUPPORTED
+ * on a constrained-transport context. */
 mhd_status mhd_prim_to_cons_adjoint(mhd_ctx *ctx, const double *V, const double *lam_U,
                                     double *lam_V);
 

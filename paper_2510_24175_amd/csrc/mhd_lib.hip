@@ -692,6 +692,7 @@ mhd_status mhd_prim_to_cons_adjoint(mhd_ctx *ctx, const double *V, const double 
     if (!ctx) return MHD_ERR_ARG;
     if (!V || !lam_U || !lam_V) return fail(ctx, MHD_ERR_ARG, "null buffer");
     if (lam_U == lam_V) return fail(ctx, MHD_ERR_ARG, "lam_V must not alias lam_U");
+    if (ctx->cfg.ct) return fail(ctx, MHD_ERR_UNSUPPORTED, "no adjoint with constrained transport");
     const int nb = (int)std::min<long long>((ctx->ncell + RED_THREADS - 1) / RED_THREADS, 8192);
     hipLaunchKernelGGL(prim_to_cons_adjoint_kernel, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, V,
                        lam_U, lam_V, ctx->ncell, 1.0 / (ctx->cfg.gamma - 1.0));
