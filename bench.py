@@ -110,13 +110,19 @@ def run_gpu(n, dtype, steps, warmup, workload="turbulence", limiter="minmod", ti
     # algorithmic HBM traffic: the first stage reads Un and writes U1
     # (18 s B/cell), every later stage reads Un and its input stage and
     # writes its output (27 s B/cell): 45 s B/cell per SSP-RK2 step, 72 s
-    # per SSP-RK3 step.  Constrained transport adds per stage the face field
-    # (3 components read with the input, 3 more with Un after the first
-    # stage, 3 written), the 6 transverse fluxes (written, read) and the 3
-    # EMFs (written, read): 36 s B/cell in the first stage, 39 s after.
-    ct = setup.get("ct", False)
-    res["alg_bytes_step"] = ((18 + 27 * (time_order - 1)) +
-                             ((36 + 39 * (time_order - 1)) if ct else 0)) * s * ncell
+    # per SSP-RK3 step.  Constrained transport, per stage: the stage kernel
+    # reads the input's 9 components and 3 faces (and Un's 9 after the first
+    # stage) and writes 6 components and 6 transverse fluxes (24 s | 33 s);
+    # the EMF pass reads 6 fluxes and writes 3 EMFs (9 s); the face pass
+    # reads 3 EMFs and the input's 3 faces (and Un's 3 after the first
+    # stage), writes 3 faces and 3 cell-field components, and in the last
+    # stage reads 6 components for the reductions (12 s | 15 s | 21 s):
+    # 45 s, 57 s and 63 s B/cell for the first, a middle and the last stage.
+    if setup.get("ct", False):
+        stages = [45] + [57] * (time_order - 2) + [63]
+        res["alg_bytes_step"] = sum(stages) * s * ncell
+    else:
+        res["alg_bytes_step"] = (18 + 27 * (time_order - 1)) * s * ncell
     res["alg_bytes_stage2"] = 27 * s * ncell
     res["hbm_frac_step"] = res["alg_bytes_step"] / (wall / steps) / (HBM_PEAK_GBS * 1e9)
     del a, b
