@@ -33,6 +33,8 @@ template <> struct Num<float> {
     static __device__ __forceinline__ float min(float a, float b) { return __builtin_fminf(a, b); }
     static __device__ __forceinline__ float max(float a, float b) { return __builtin_fmaxf(a, b); }
     static __device__ __forceinline__ float copysign(float a, float b) { return __builtin_copysignf(a, b); }
+    // minmod(a, b) as the median of a, b and 0 (one instruction)
+    static __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
     static constexpr float eps = 1.1920928955078125e-7f;
     static constexpr float weno_eps = 1e-30f;  // normal, with a finite reciprocal
     static constexpr float big = 3.0e38f;
@@ -46,6 +48,10 @@ template <> struct Num<double> {
     static __device__ __forceinline__ double min(double a, double b) { return __builtin_fmin(a, b); }
     static __device__ __forceinline__ double max(double a, double b) { return __builtin_fmax(a, b); }
     static __device__ __forceinline__ double copysign(double a, double b) { return __builtin_copysign(a, b); }
+    static __device__ __forceinline__ double minmod(double a, double b)
+    {
+        return (a * b > 0.0) ? __builtin_copysign(__builtin_fmin(__builtin_fabs(a), __builtin_fabs(b)), a) : 0.0;
+    }
     static constexpr double eps = 2.220446049250313e-16;
     static constexpr double weno_eps = 1e-40;
     static constexpr double big = 1.0e300;
@@ -88,13 +94,14 @@ __device__ __forceinline__ bool cons_to_prim(const T *u, const Phys<T> &ph, T *v
 }
 
 // Limited slope from the backward difference a and the forward difference b:
-// minmod(a, b), or MC = minmod(2a, 2b, (a+b)/2).
-// The limiter is a compile-time parameter of the kernels.
+// minmod(a, b) (zero unless a and b have the same sign, else the one of
+// smaller magnitude), or MC = minmod(2a, 2b, (a+b)/2) =
+// minmod(2a, minmod(2b, (a+b)/2)).  The limiter is a compile-time parameter
+// of the kernels.
 template <int LIM, typename T> __device__ __forceinline__ T limited_slope(T a, T b)
 {
-    T m = Num<T>::min(Num<T>::abs(a), Num<T>::abs(b));
-    if (LIM == LIM_MC) m = Num<T>::min(T(2) * m, T(0.5) * Num<T>::abs(a + b));
-    return (a * b > T(0)) ? Num<T>::copysign(m, a) : T(0);
+    if (LIM == LIM_MC) return Num<T>::minmod(T(2) * a, Num<T>::minmod(T(2) * b, T(0.5) * (a + b)));
+    return Num<T>::minmod(a, b);
 }
 
 // WENO-Z face values of one cell (Borges, Carmona, Costa & Don 2008; p = 1,
@@ -259,7 +266,11 @@ __device__ __forceinline__ void hll_flux(const RState<T> &L, const RState<T> &R,
     const T sR = Num<T>::max(Num<T>::max(L.u + cL, R.u + cR), T(0));
     const T id = Num<T>::rcp(sR - sL);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) F[k] = (sR * FL[k] - sL * FR[k] + sL * sR * (UR[k] - UL[k])) * id;
+    for (int k = 0; k < 8; ++k) {
+        // slot 5 (B_n) is unused: the interface solve supplies that flux
+        if (k == 5) F[k] = T(0);
+        else F[k] = (sR * FL[k] - sL * FR[k] + sL * sR * (UR[k] - UL[k])) * id;
+    }
 }
 
 // One side of the HLLD single-star state (Miyoshi & Kusano 2005): density,
@@ -283,12 +294,13 @@ __device__ __forceinline__ void hlld_star(const RState<T> &s, T S, T sM, Star<T>
     const T D = mm - bn2;
     const bool degenerate = Num<T>::abs(D) <= T(16) * Num<T>::eps * (Num<T>::abs(mm) + bn2);
     const T iD = Num<T>::rcp(D);
-    const T cv = s.bn * (sM - s.u) * iD;
-    const T cb = (m * o.su - bn2) * iD;
-    o.v1 = degenerate ? s.v1 : s.v1 - s.b1 * cv;
-    o.v2 = degenerate ? s.v2 : s.v2 - s.b2 * cv;
-    o.b1 = degenerate ? s.b1 : s.b1 * cb;
-    o.b2 = degenerate ? s.b2 : s.b2 * cb;
+    // a degenerate side keeps its tangential state: cv = 0, cb = 1
+    const T cv = degenerate ? T(0) : s.bn * (sM - s.u) * iD;
+    const T cb = degenerate ? T(1) : (m * o.su - bn2) * iD;
+    o.v1 = s.v1 - s.b1 * cv;
+    o.v2 = s.v2 - s.b2 * cv;
+    o.b1 = s.b1 * cb;
+    o.b2 = s.b2 * cb;
     o.isq = Num<T>::rsqrt(o.rho);
     o.sq = o.rho * o.isq;
 }
@@ -355,8 +367,14 @@ __device__ __forceinline__ void hlld_flux(const RState<T> &L, const RState<T> &R
     rstate_flux(S, f, u);
     const T us[8] = {st.rho, st.rho * sM, st.rho * st.v1, st.rho * st.v2, Es, bn, st.b1, st.b2};
     const T uss[8] = {st.rho, st.rho * sM, st.rho * v1, st.rho * v2, Ess, bn, b1, b2};
+    // rho, the normal momentum and B_n agree in the single- and double-star
+    // states; slot 5 (B_n) is unused
 #pragma unroll
-    for (int k = 0; k < 8; ++k) F[k] = f[k] + a1 * (us[k] - u[k]) + a2 * (uss[k] - us[k]);
+    for (int k = 0; k < 8; ++k) {
+        if (k == 5) F[k] = T(0);
+        else if (k <= 1) F[k] = f[k] + a1 * (us[k] - u[k]);
+        else F[k] = f[k] + a1 * (us[k] - u[k]) + a2 * (uss[k] - us[k]);
+    }
 }
 
 // Select a[d] for d in {0,1,2} without indexing a register array (the
