@@ -176,6 +176,26 @@ def run_adjoint_ratio(n, dtype, steps):
             "backward_incl_recompute_ratio": round((adj + fwd) / fwd, 3)}
 
 
+def copy_bandwidth(mib=2048, reps=5):
+    """Achievable HBM bandwidth: a plain device-to-device copy of MIB MiB
+    (read + write bytes per copy over its event-timed duration)."""
+    import torch
+
+    a = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(n_sample=256, steps=4):
     """FP64 CPU oracle on a bounded sample of the same workload: the same
     turbulence generator (modes, spectra, amplitudes) on an n_sample^3
@@ -193,10 +213,17 @@ def cpu_baseline(n_sample=256, steps=4):
         U = o.step(U, dt, ch)
     wall = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {
         "value": n_sample ** 3 * steps / wall / 1e6,
         "unit": "Mcell-updates/s",
         "cores": threads,
+        "cpu_model": model,
         "kind": "oracle",
         "sample": f"turbulence {n_sample}^3 (same generator, FP64, PLM minmod + HLLD + GLM), "
                   f"{steps} full RK2 steps incl. CFL, {wall:.1f} s wall",
@@ -272,6 +299,10 @@ def main():
         "traffic": traffic,
         "avg_launch_ms": round(r32["stage2_ms"], 4),
     }
+    # second denominator: what a plain device copy achieves on this GPU
+    cgbs = copy_bandwidth()
+    out["roofline"]["copy_gbs"] = round(cgbs, 1)
+    out["roofline"]["frac_of_copy"] = round(ach / cgbs, 4)
     if cnt and cnt.get("valu_wave_insts"):
         # the kernel is bound by VALU issue, not HBM: wave64 VALU instructions
         # (SQ_INSTS_VALU) x 4 cycles each on a 16-lane SIMD, against 1024
