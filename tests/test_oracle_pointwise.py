@@ -93,6 +93,23 @@ def test_limiter_closed_forms():
     assert C.limited_slope("mc", -0.1, -5.0) == -0.2
 
 
+def test_limiter_median_forms():
+    """The FP32 kernels evaluate minmod(a, b) as the median of a, b and 0 and
+    MC as minmod(2a, minmod(2b, (a+b)/2)); both identities hold exactly
+    against the oracle's limiters (random pairs, ties, zeros, sign changes)
+    wherever a*b does not underflow.  Where it does, the oracle's sign test
+    a*b > 0 reads zero and the median keeps the smaller argument: a
+    difference no larger than that argument (below 1e-22 in FP32)."""
+    rng = np.random.default_rng(5)
+    pairs = [(x, y) for x, y in rng.normal(size=(400, 2)) * np.exp(rng.uniform(-20, 20, size=(400, 1)))]
+    pairs += [(1.0, 1.0), (-2.0, -2.0), (0.0, 0.0), (0.0, -1.0), (3.0, -3.0), (-0.0, 2.0)]
+    med = lambda x, y: float(np.median([x, y, 0.0]))
+    for a, b in pairs:
+        assert med(a, b) == C.limited_slope("minmod", a, b)
+        assert med(2 * a, med(2 * b, 0.5 * (a + b))) == C.limited_slope("mc", a, b)
+    assert med(1e-300, 2e-300) == 1e-300 and C.limited_slope("minmod", 1e-300, 2e-300) == 0.0
+
+
 def test_limiter_tvd_on_monotone_step():
     """Face values of a limited monotone profile stay within the neighbours."""
     rng = np.random.default_rng(0)
