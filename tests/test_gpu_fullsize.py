@@ -127,12 +127,12 @@ def test_orszag_tang_1024():
     # Without floors this scheme (PLM minmod + HLLD + GLM, SSP-RK2) loses
     # pressure positivity on this setup at 1024^2 before t = 0.5 for Courant
     # numbers 0.2 - 0.3 in FP64 (the FP64 oracle at 0.3 fails at t = 0.398, as
-    # the GPU path does).  At 0.15 and 0.1 the first stage of a step near
-    # t = 0.44 takes a near-vacuum cell's pressure to within rounding of zero:
-    # two builds whose states agree to 1e-15 through step 6500 (the HLLD flux
-    # written with and without terms that are exactly zero) part there, one
-    # reaching t = 0.5 and the other stopping at t = 0.4386.  The long run
-    # therefore ends at t = 0.4 (Courant number 0.15).  The point symmetry
+    # the GPU path does).  At 0.15 the run is on the edge near t = 0.44: the
+    # FP64 oracle reaches t = 0.5, while two GPU builds whose steps agree to
+    # 3e-16 on the same input (the HLLD flux written with and without terms
+    # that are exactly zero) follow trajectories that agree to 1e-15 through
+    # step 6500 and then part, one reaching t = 0.5 and the other stopping at
+    # t = 0.4386.  The long run therefore ends at t = 0.4 (Courant number 0.15).  The point symmetry
     # holds up to rounding differences that the shock interactions amplify:
     # the FP64 oracle's own asymmetry on this setup at 512^2 (4372 steps) is
     # 4.3e-6, and the GPU FP64 state there differs from the oracle's by 6e-6
