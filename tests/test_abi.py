@@ -107,6 +107,26 @@ def test_invalid_geometry_is_rejected():
     assert _init(cfg) == mhd.MHD_ERR_ARG
 
 
+@pytest.mark.parametrize("n", [(0, 8, 8), (-5, 8, 8), (8, 0, 8), ((1 << 30) + 1, 8, 8),
+                               (1 << 14, 1 << 14, 1 << 13)])
+def test_empty_negative_and_oversized_grids_are_rejected(n):
+    # empty or negative axes, an axis beyond 2^30 cells, more than 2^40 cells
+    cfg = _base()
+    for d in range(3):
+        cfg.n[d] = n[d]
+    assert _init(cfg) == mhd.MHD_ERR_ARG
+
+
+def test_constrained_transport_grid_limit():
+    # constrained-transport passes index cells in 32 bits: 2^31 cells or more
+    # are refused (1300^3 = 2.197e9)
+    s, _ = W.orszag_tang_3d_ct(8)
+    cfg = mhd.make_config(s, "f32")
+    for d in range(3):
+        cfg.n[d] = 1300
+    assert _init(cfg) == mhd.MHD_ERR_ARG
+
+
 def test_null_arguments():
     lib = mhd.load_library()
     assert lib.mhd_init(None, None, None) == mhd.MHD_ERR_ARG
