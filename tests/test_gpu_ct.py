@@ -120,21 +120,40 @@ def test_ct_uniform_state(torch_cuda, time_order):
         assert torch.allclose(U, U0, rtol=1e-14, atol=0.0)
 
 
+def _sample_cells_352(n, rng, count=24):
+    # x tiles of 64 (a partial one from 320), y tiles of 4 or 8 rows, z chunks
+    # of 32 planes: cells on both sides of those boundaries, corners, random
+    cells = [(0, 0, 0), (n - 1, n - 1, n - 1), (63, 64, 31), (64, 63, 32), (319, 7, 8),
+             (320, 8, 7), (n - 1, 3, 4), (0, n - 1, 63), (255, 256, 320), (351, 300, 32)]
+    while len(cells) < count:
+        cells.append(tuple(int(v) for v in rng.integers(0, n, 3)))
+    return [(k, j, i) for (i, j, k) in cells]
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_orszag_tang_3d_ct_352(torch_cuda, dtype):
     """The paper's weak-scaling configuration per GPU (704 x 704 x 352 per
     four-GPU node = 352^3), WENO-Z + HLLD + SSP-RK3 with constrained
-    transport, in the launch configuration the bench times: two steps,
-    checked for the face divergence and the FP64 conservation sums."""
+    transport, in the launch configuration the bench times.  The first step
+    (the oracle's full-grid dt and c_h) is compared at sampled cells, all 12
+    components, with the FP64 oracle on a periodic 21^3 window around each
+    cell (a step at a cell depends on cells within 9 along each axis, pinned
+    in the oracle tests); the GPU's CFL against the oracle's; after a second
+    step the face divergence and the FP64 conservation sums."""
     torch = torch_cuda
     from paper_2510_24175_amd.mhd import Context
     n = 352
     _say(f"[gpu-ct] Orszag-Tang 3D CT {n}^3 {dtype}")
     s, V = W.orszag_tang_3d_ct(n)
+    o = C.Oracle(s)
+    Uo = o.prim_to_cons(V)
+    dt, ch = o.cfl(Uo)
     ctx = Context(s, dtype)
     U = ctx.prim_to_cons(torch.from_numpy(V).cuda())
     del V
-    dt, ch = ctx.cfl_dt(U)
+    dtg, chg = ctx.cfl_dt(U)
+    tol_cfl = 1e-14 if dtype == "f64" else 1e-6
+    assert abs(dtg / dt - 1) < tol_cfl and abs(chg / ch - 1) < tol_cfl, (dtg, dt, chg, ch)
     out = torch.empty_like(U)
     ctx.step(U, out, dt, ch, 1.0)
     _, _, sums1 = ctx.step_info()
@@ -142,8 +161,28 @@ def test_orszag_tang_3d_ct_352(torch_cuda, dtype):
     ctx.step(out, U, dt2, ch2, 1.0)
     _, _, sums2 = ctx.step_info()
     torch.cuda.synchronize()
+    # sampled cells of the first step against the oracle's window step
+    r = 10
+    sub = W.make_setup("window", 3, (2 * r + 1,) * 3, gamma=s["gamma"], cfl=s["cfl"],
+                       riemann=s["riemann"], limiter="wenoz", time_order=3, glm=False,
+                       hi=tuple((2 * r + 1) / n for _ in range(3)))
+    sub["ct"] = True
+    ow = C.Oracle(sub)
+    rng = np.random.default_rng(12)
+    comp_scale = np.maximum(np.abs(Uo).max(axis=(1, 2, 3)), 1e-2)
+    tol = TOL[dtype]
+    worst = 0.0
+    for (k, j, i) in _sample_cells_352(n, rng):
+        idx = np.ix_(range(12), [(k + a) % n for a in range(-r, r + 1)],
+                     [(j + a) % n for a in range(-r, r + 1)], [(i + a) % n for a in range(-r, r + 1)])
+        ref = ow.step(Uo[idx], dt, ch, 1.0)[:, r, r, r]
+        got = out[:, k, j, i].double().cpu().numpy()
+        err = (np.abs(got - ref) / comp_scale).max()
+        worst = max(worst, err)
+        assert err <= tol, ((k, j, i), got, ref)
+    _say(f"    worst sampled-cell error (per-component scaled): {worst:.2e}")
+    del out
     Ug = U.double().cpu().numpy()
-    o = C.Oracle(s)
     div = np.abs(o.div_b(Ug)).max() * min(o.dx) / np.abs(Ug[9:]).max()
     scale = np.array([np.abs(Ug[q]).sum() for q in range(9)]) * o.cell_volume
     for v0 in (1, 5):

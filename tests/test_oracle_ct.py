@@ -121,3 +121,29 @@ def test_config_checks():
     s["glm"] = True
     with pytest.raises(C.OracleError):
         C.Oracle(s).prim_to_cons(V)  # GLM and CT together are refused
+
+
+def test_window_reproduces_full_grid_cell():
+    """A WENO-Z SSP-RK3 step with constrained transport at a cell depends on
+    cells within 9 along each axis: a periodic 21^3 window around the cell
+    gives the full-grid value at its centre bit for bit, a 17^3 one does not.
+    This is how the full-size parity test samples the oracle."""
+    n = 32
+    s, V = W.orszag_tang_3d_ct(n)
+    o = C.Oracle(s)
+    U0 = o.prim_to_cons(V)
+    dt, ch = o.cfl(U0)
+    full = o.step(U0, dt, ch, 1.0)
+    cells = [(0, 0, 0), (7, 3, 15), (31, 31, 8), (16, 20, 5)]
+    for r, exact in ((10, True), (8, False)):
+        sub = W.make_setup("window", 3, (2 * r + 1,) * 3, gamma=s["gamma"], cfl=s["cfl"],
+                           riemann=s["riemann"], limiter="wenoz", time_order=3, glm=False,
+                           hi=tuple((2 * r + 1) / n for _ in range(3)))
+        sub["ct"] = True
+        ow = C.Oracle(sub)
+        worst = 0.0
+        for (k, j, i) in cells:
+            idx = np.ix_(range(12), [(k + a) % n for a in range(-r, r + 1)],
+                         [(j + a) % n for a in range(-r, r + 1)], [(i + a) % n for a in range(-r, r + 1)])
+            worst = max(worst, np.abs(ow.step(U0[idx], dt, ch, 1.0)[:, r, r, r] - full[:, k, j, i]).max())
+        assert (worst == 0.0) == exact, (r, worst)

@@ -272,3 +272,29 @@ def test_cpa_3d_diagonal_third_order():
     e16, e32 = err(16), err(32)
     assert math.log2(e16 / e32) >= 2.7, (e16, e32)
     assert e32 <= 2e-5, e32
+
+
+def test_window_reproduces_full_grid_cell():
+    """A WENO-Z SSP-RK3 step at a cell depends on cells within 9 along each
+    axis (3 per stage): a 21^3 window around the cell, stepped with outflow
+    boundaries, gives the full-grid value at its centre bit for bit, a 17^3
+    one does not.  This is how the 416^3 parity test samples the oracle."""
+    n = 24
+    s, V = W.orszag_tang_3d(n)
+    o = C.Oracle(s)
+    U0 = o.prim_to_cons(V)
+    dt, ch = o.cfl(U0)
+    dmp = o.damp(dt, ch)
+    full = o.step(U0, dt, ch, dmp)
+    cells = [(0, 0, 0), (7, 3, 15), (23, 23, 8), (12, 20, 5)]
+    for r, exact in ((10, True), (8, False)):
+        sub = W.make_setup("window", 3, (2 * r + 1,) * 3, gamma=s["gamma"], cfl=s["cfl"],
+                           riemann=s["riemann"], limiter="wenoz", time_order=3,
+                           bc=(("outflow", "outflow"),) * 3, hi=tuple((2 * r + 1) / n for _ in range(3)))
+        ow = C.Oracle(sub)
+        worst = 0.0
+        for (k, j, i) in cells:
+            idx = np.ix_(range(9), [(k + a) % n for a in range(-r, r + 1)],
+                         [(j + a) % n for a in range(-r, r + 1)], [(i + a) % n for a in range(-r, r + 1)])
+            worst = max(worst, np.abs(ow.step(U0[idx], dt, ch, dmp)[:, r, r, r] - full[:, k, j, i]).max())
+        assert (worst == 0.0) == exact, (r, worst)
