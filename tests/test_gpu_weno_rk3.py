@@ -209,7 +209,8 @@ def test_orszag_tang_3d_416_sampled(torch_cuda, dtype):
     as timed.  One SSP-RK3 step compared at sampled cells (tile, partial-tile
     and z-chunk boundaries, random) with the FP64 oracle on a 21^3 window
     around each cell (a WENO-Z SSP-RK3 step at a cell depends on cells within
-    9 along each axis); conservation of the FP64 sums over two steps; the
+    9 along each axis, pinned in the oracle tests); conservation of the FP64
+    sums over two steps; the
     GPU's CFL against the oracle's full-grid one."""
     torch = torch_cuda
     from paper_2510_24175_amd.mhd import Context
