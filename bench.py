@@ -52,7 +52,7 @@ def measured_counters(kernel_key):
     with open(path) as f:
         data = json.load(f)
     ent = data.get(kernel_key)
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    if not isinstance(ent, dict) or ent.get("source_hash") != kernel_source_hash():
         return None
     return ent
 
