@@ -65,7 +65,7 @@ mhd_status fail(mhd_ctx *ctx, mhd_status st, const std::string &msg)
 // workgroups (12 waves) per compute unit at the 168-VGPR budget; measured
 // faster than 6 rows (two workgroups of 6 waves) by a third and than 8 rows
 // (one workgroup of 8 waves) by 13%.  FP32 WENO-Z: 8 rows, one workgroup of
-// 8 waves and 124 KB of LDS per compute unit; the three-cell y halo costs
+// 8 waves and 155 KB of LDS per compute unit; the three-cell y halo costs
 // half as much per cell as with 4 rows (measured 9% faster).  FP64 (register
 // bound at one wave per SIMD, WENO-Z at 140 KB of LDS): 4 rows.  1D: 1 row.
 template <typename T, int LIM, int NDIM> constexpr int tile_rows()

@@ -152,12 +152,14 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Waves per SIMD the kernels are compiled for.  FP32 PLM: register budget
-// 168 (with 4-wave workgroups three of them share a compute unit); FP32
-// WENO-Z, whose 8-row workgroups take 124 KB of LDS (one per compute unit),
-// 256.  FP64 PLM: 2 (256 registers; the HLLD kernels spill 26-83 of them,
-// and still run 11% faster than at one wave per SIMD without spills).  FP64
-// WENO-Z: 1 (140 KB of LDS allows one 4-wave workgroup per compute unit).
+// Waves per SIMD the kernels are compiled for.  FP32 PLM: 3, a budget of 168
+// registers (stage 1 needs 127, so four 4-wave workgroups share a compute
+// unit; the last stage 165, three).  FP32 WENO-Z: 2 (256 registers; its
+// 8-row workgroups take 155 KB of LDS, one per compute unit).  FP64 PLM: 2
+// (256 registers; the HLLD kernels spill some of them, and still run 11%
+// faster than at one wave per SIMD without spills).  FP64 WENO-Z: 1 (140 KB
+// of LDS, the fluxes laid over the primitive plane, allows one 4-wave
+// workgroup per compute unit).
 template <typename T, int LIM> constexpr int stage_min_waves()
 {
     return sizeof(T) == 4 ? (LIM == LIM_WENOZ ? 2 : 3) : (LIM == LIM_WENOZ ? 1 : 2);
