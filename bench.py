@@ -34,11 +34,36 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 METRIC = "Mcell-updates/s + % HBM roofline (FP32 vs FP64), adjoint/forward time ratio"
 
 
+def _code_only(text):
+    """C++ source without comments and blank lines (string literals kept)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"':
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return "\n".join(ln.rstrip() for ln in "".join(out).splitlines() if ln.strip())
+
+
 def kernel_source_hash():
+    """Hash of the kernel sources' code (comments and blank lines do not
+    count: the stored counters stay valid across comment edits)."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_2510_24175_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
