@@ -48,9 +48,11 @@ template <> struct Num<double> {
     static __device__ __forceinline__ double min(double a, double b) { return __builtin_fmin(a, b); }
     static __device__ __forceinline__ double max(double a, double b) { return __builtin_fmax(a, b); }
     static __device__ __forceinline__ double copysign(double a, double b) { return __builtin_copysign(a, b); }
+    // minmod(a, b) as the median of a, b and 0 (no FP64 median instruction:
+    // four min/max)
     static __device__ __forceinline__ double minmod(double a, double b)
     {
-        return (a * b > 0.0) ? __builtin_copysign(__builtin_fmin(__builtin_fabs(a), __builtin_fabs(b)), a) : 0.0;
+        return __builtin_fmax(__builtin_fmin(a, b), __builtin_fmin(__builtin_fmax(a, b), 0.0));
     }
     static constexpr double eps = 2.220446049250313e-16;
     static constexpr double weno_eps = 1e-40;

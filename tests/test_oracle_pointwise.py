@@ -94,12 +94,13 @@ def test_limiter_closed_forms():
 
 
 def test_limiter_median_forms():
-    """The FP32 kernels evaluate minmod(a, b) as the median of a, b and 0 and
+    """The kernels evaluate minmod(a, b) as the median of a, b and 0 and
     MC as minmod(2a, minmod(2b, (a+b)/2)); both identities hold exactly
     against the oracle's limiters (random pairs, ties, zeros, sign changes)
     wherever a*b does not underflow.  Where it does, the oracle's sign test
     a*b > 0 reads zero and the median keeps the smaller argument: a
-    difference no larger than that argument (below 1e-22 in FP32)."""
+    difference no larger than that argument (below 1e-22 in FP32, 1e-154 in
+    FP64)."""
     rng = np.random.default_rng(5)
     pairs = [(x, y) for x, y in rng.normal(size=(400, 2)) * np.exp(rng.uniform(-20, 20, size=(400, 1)))]
     pairs += [(1.0, 1.0), (-2.0, -2.0), (0.0, 0.0), (0.0, -1.0), (3.0, -3.0), (-0.0, 2.0)]
