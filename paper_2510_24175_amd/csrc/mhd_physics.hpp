@@ -7,7 +7,8 @@
 // A face normal to axis d is solved in the cyclic frame (n, t1, t2) =
 // (d, d+1, d+2) mod 3.  Everything is templated on the arithmetic type T
 // (float or double); reciprocals and square roots go through Num<T>, which
-// uses the hardware approximations in FP32 and IEEE operations in FP64.
+// uses the hardware approximations in FP32, and in FP64 IEEE square roots and
+// Newton-refined reciprocals.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,9 +42,18 @@ template <> struct Num<float> {
 };
 
 template <> struct Num<double> {
-    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    // reciprocal: the hardware estimate refined by two Newton-Raphson steps
+    // (e = 1 - x r, r <- r + r e), within an ulp of 1/x for normal x
+    static __device__ __forceinline__ double rcp(double x)
+    {
+        double r = __builtin_amdgcn_rcp(x);
+        double e = __builtin_fma(-x, r, 1.0);
+        r = __builtin_fma(r, e, r);
+        e = __builtin_fma(-x, r, 1.0);
+        return __builtin_fma(r, e, r);
+    }
     static __device__ __forceinline__ double sqrt(double x) { return __builtin_sqrt(x); }
-    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
+    static __device__ __forceinline__ double rsqrt(double x) { return rcp(__builtin_sqrt(x)); }
     static __device__ __forceinline__ double abs(double x) { return __builtin_fabs(x); }
     static __device__ __forceinline__ double min(double a, double b) { return __builtin_fmin(a, b); }
     static __device__ __forceinline__ double max(double a, double b) { return __builtin_fmax(a, b); }
