@@ -95,8 +95,10 @@ Launch plan_stage(const mhd_ctx *ctx, int ty, long long min_blocks = 2048)
         // the grid would otherwise leave compute units idle.  FP64 WENO-Z
         // (one 4-wave workgroup per compute unit) starts at 32 planes:
         // measured 7% faster at 416^3 and 10% with constrained transport at
-        // 352^3 than 64 (FP32 and PLM: no gain)
-        kz = (ctx->cfg.dtype == MHD_F64 && ctx->cfg.limiter == MHD_WENOZ) ? 32 : 64;
+        // 352^3 than 64; FP32 constrained transport at 16 planes, 2% faster
+        // at 352^3 (FP32 GLM and PLM: no gain)
+        const bool f64 = ctx->cfg.dtype == MHD_F64;
+        kz = (f64 && ctx->cfg.limiter == MHD_WENOZ) ? 32 : ((!f64 && ctx->cfg.ct) ? 16 : 64);
         while (kz > 4 && tiles * ((ctx->n[2] + kz - 1) / kz) < min_blocks) kz >>= 1;
     }
     L.kz = kz;
