@@ -79,6 +79,10 @@ def lib():
         L.orc_hlld_fan.restype = None
         L.orc_rotated_flux.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, dp]
         L.orc_rotated_flux.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -225,6 +229,16 @@ class Oracle:
         for dt, ch, dmp in history:
             U = self.step(U, dt, ch, dmp)
         return U
+
+
+def set_threads(n):
+    """OpenMP team size of the oracle's loops (n > 0)."""
+    lib().orc_set_threads(int(n))
+
+
+def threads():
+    """OpenMP team size the oracle's loops use."""
+    return int(lib().orc_threads())
 
 
 # -- pointwise pieces used by the pin tests ---------------------------------

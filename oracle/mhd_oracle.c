@@ -63,6 +63,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <float.h>
+#include <omp.h>
 
 #define NV 9
 /* primitive slots */
@@ -932,3 +933,12 @@ void orc_rotated_flux(int riemann, const double *qL, const double *qR, double ga
     else
         hll_flux(qL, qR, gamma, F);
 }
+
+/* host threads of the parallel loops (for the timed CPU baseline): set and
+ * query the OpenMP team size */
+void orc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
+
+int orc_threads(void) { return omp_get_max_threads(); }

@@ -32,7 +32,8 @@ struct mhd_ctx {
     void *ct_emf = nullptr;      // constrained transport: [3] edge EMFs
     double *part = nullptr;      // NPART x part_cap block partials
     int part_cap = 0;
-    double *result = nullptr;    // device NPART doubles
+    double *result = nullptr;    // device NPART doubles: reductions of the last mhd_step output
+    double *cfl_result = nullptr; // device NPART doubles: the last mhd_cfl_dt reduction
     int *flag = nullptr;         // device non-physical flag
     double *host_res = nullptr;  // pinned NPART doubles + flag word
     double *lam1 = nullptr;      // adjoint: FP64 stage cotangent
@@ -48,17 +49,22 @@ namespace {
 
 constexpr int CFL_MAX_BLOCKS = 4096;
 
-mhd_status fail(mhd_ctx *ctx, mhd_status st, const std::string &msg)
+mhd_status fail(mhd_ctx *ctx, mhd_status st, const char *msg)
 {
     if (ctx) ctx->err = msg;
     return st;
 }
 
-#define HIP_TRY(ctx, call)                                                                     \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail((ctx), MHD_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+mhd_status fail_hip(mhd_ctx *ctx, const char *what, hipError_t e)
+{
+    if (ctx) ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+    return MHD_ERR_HIP;
+}
+
+#define HIP_TRY(ctx, call)                                \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return fail_hip((ctx), #call, e_); \
     } while (0)
 
 // Stage tile rows per workgroup (one wave per row).  FP32 PLM: 4 rows, three
@@ -444,15 +450,16 @@ mhd_status launch_cfl(mhd_ctx *ctx, const T *U)
     }
     HIP_TRY(ctx, hipGetLastError());
     hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(RED_THREADS), 0, ctx->stream,
-                       (const double *)ctx->part, nb, ctx->result);
+                       (const double *)ctx->part, nb, ctx->cfl_result);
     HIP_TRY(ctx, hipGetLastError());
     return MHD_OK;
 }
 
-// Copy the result words back, wait, and report (and clear) the flag.
-mhd_status sync_results(mhd_ctx *ctx)
+// Copy the result words of one reduction (the step's or the standalone
+// CFL's) back, wait, and report (and clear) the flag.
+mhd_status sync_results(mhd_ctx *ctx, const double *result)
 {
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_res, ctx->result, NPART * sizeof(double),
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_res, result, NPART * sizeof(double),
                                 hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->host_res + NPART, ctx->flag, sizeof(int), hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -471,7 +478,7 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 // Validates a configuration: MHD_ERR_ARG for invalid fields,
 // MHD_ERR_UNSUPPORTED for the adjoint of WENO-Z or SSP-RK3 (not built).
-mhd_status check_config(const mhd_config *c, std::string &why)
+mhd_status check_config(const mhd_config *c, const char *&why)
 {
     if (!c) return why = "config is NULL", MHD_ERR_ARG;
     if (c->ndim < 1 || c->ndim > 3) return why = "ndim must be 1, 2 or 3", MHD_ERR_ARG;
@@ -535,6 +542,7 @@ void free_ctx(mhd_ctx *ctx)
     if (ctx->ct_emf) (void)hipFree(ctx->ct_emf);
     if (ctx->part) (void)hipFree(ctx->part);
     if (ctx->result) (void)hipFree(ctx->result);
+    if (ctx->cfl_result) (void)hipFree(ctx->cfl_result);
     if (ctx->flag) (void)hipFree(ctx->flag);
     if (ctx->host_res) (void)hipHostFree(ctx->host_res);
     if (ctx->lam1) (void)hipFree(ctx->lam1);
@@ -570,7 +578,7 @@ mhd_status mhd_timing_start(mhd_ctx *ctx, int32_t capacity)
         if (r != hipSuccess) {
             e = nullptr;
             destroy_events(ctx);
-            return fail(ctx, MHD_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(r));
+            return fail_hip(ctx, "hipEventCreate", r);
         }
     }
     ctx->timed_cap = capacity;
@@ -602,7 +610,7 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
 {
     if (!out) return MHD_ERR_ARG;
     *out = nullptr;
-    std::string why;
+    const char *why = "";
     const mhd_status cst = check_config(cfg, why);
     if (cst != MHD_OK) return cst;
     int ndev = 0;
@@ -643,6 +651,7 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
     if (e == hipSuccess && cfg->ct) e = hipMalloc(&ctx->ct_emf, (size_t)3 * ctx->ncell * ctx->elem);
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->part, (size_t)NPART * ctx->part_cap * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->result, NPART * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->cfl_result, NPART * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->flag, sizeof(int));
     if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->host_res, (NPART + 1) * sizeof(double));
     if (e == hipSuccess && (cfg->flags & MHD_FLAG_ADJOINT))
@@ -714,7 +723,7 @@ mhd_status mhd_cfl_dt(mhd_ctx *ctx, const void *U, double out[2])
     mhd_status st = ctx->cfg.dtype == MHD_F32 ? launch_cfl<float>(ctx, (const float *)U)
                                                : launch_cfl<double>(ctx, (const double *)U);
     if (st != MHD_OK) return st;
-    st = sync_results(ctx);
+    st = sync_results(ctx, ctx->cfl_result);
     if (st != MHD_OK) return st;
     out[0] = ctx->cfg.cfl / ctx->host_res[0];
     out[1] = ctx->host_res[1];
@@ -745,11 +754,22 @@ mhd_status mhd_step_info(mhd_ctx *ctx, double out[11])
     if (!ctx) return MHD_ERR_ARG;
     if (!out) return fail(ctx, MHD_ERR_ARG, "null buffer");
     if (!ctx->have_step) return fail(ctx, MHD_ERR_ARG, "no step has run on this context");
-    mhd_status st = sync_results(ctx);
+    mhd_status st = sync_results(ctx, ctx->result);
     if (st != MHD_OK) return st;
     out[0] = ctx->cfg.cfl / ctx->host_res[0];
     out[1] = ctx->host_res[1];
     for (int q = 0; q < NQ; ++q) out[2 + q] = ctx->host_res[2 + q] * ctx->cell_volume;
+    return MHD_OK;
+}
+
+mhd_status mhd_get_sums(mhd_ctx *ctx, double out[9])
+{
+    if (!ctx) return MHD_ERR_ARG;
+    if (!out) return fail(ctx, MHD_ERR_ARG, "null buffer");
+    if (!ctx->have_step) return fail(ctx, MHD_ERR_ARG, "no step has run on this context");
+    mhd_status st = sync_results(ctx, ctx->result);
+    if (st != MHD_OK) return st;
+    for (int q = 0; q < NQ; ++q) out[q] = ctx->host_res[2 + q] * ctx->cell_volume;
     return MHD_OK;
 }
 

@@ -80,6 +80,7 @@ def load_library():
         "mhd_cfl_dt": ([vp, vp, dp], ctypes.c_int),
         "mhd_step": ([vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], ctypes.c_int),
         "mhd_step_info": ([vp, dp], ctypes.c_int),
+        "mhd_get_sums": ([vp, dp], ctypes.c_int),
         "mhd_step_adjoint": ([vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
                              ctypes.c_int),
         "mhd_prim_to_cons_adjoint": ([vp, vp, vp, vp], ctypes.c_int),
@@ -223,6 +224,12 @@ class Context:
         out = (ctypes.c_double * 11)()
         self._check(self.lib.mhd_step_info(self.handle, out), "mhd_step_info")
         return out[0], out[1], list(out[2:11])
+
+    def get_sums(self):
+        """FP64 conservation sums (9) of the last step's output."""
+        out = (ctypes.c_double * 9)()
+        self._check(self.lib.mhd_get_sums(self.handle, out), "mhd_get_sums")
+        return list(out)
 
     def step_adjoint(self, Un, U1, lam_next, lam_n, dt, ch, damp):
         self._check(self.lib.mhd_step_adjoint(self.handle, self._ptr(Un, what="Un"),

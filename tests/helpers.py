@@ -31,6 +31,40 @@ def rel_l1(gpu, ref, ch=None):
     return out
 
 
+def rel_l1_own(gpu, ref):
+    """Relative L1 error of each of the 9 components against its own size,
+    sum|q - q_ref| / sum|q_ref| (no floor; a component that is zero in the
+    reference reports its absolute L1 error)."""
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    out = np.empty(gpu.shape[0])
+    for q in range(gpu.shape[0]):
+        den = np.abs(ref[q]).sum()
+        num = np.abs(gpu[q] - ref[q]).sum()
+        out[q] = num / den if den > 0 else num
+    return out
+
+
+def max_rel(gpu, ref):
+    """Element-wise error of each of the 8 MHD components: max|q - q_ref|
+    over the grid divided by max|q_ref| (the largest magnitude of the
+    component's vector for m and B, so a component that is zero somewhere
+    or everywhere is measured against its vector's scale).  Returns 8
+    values."""
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    amax = [np.abs(ref[q]).max() for q in range(8)]
+    out = np.empty(8)
+    for q in range(8):
+        den = amax[q]
+        if q in (1, 2, 3, 5, 6, 7):
+            v0 = 1 if q < 4 else 5
+            den = max(amax[v0], amax[v0 + 1], amax[v0 + 2])
+        num = np.abs(gpu[q] - ref[q]).max()
+        out[q] = num / den if den > 0 else num
+    return out
+
+
 def have_gpu():
     try:
         import torch

@@ -132,6 +132,8 @@ def test_null_arguments():
     assert lib.mhd_init(None, None, None) == mhd.MHD_ERR_ARG
     assert lib.mhd_step(None, None, None, None, 1.0, 1.0, 1.0) == mhd.MHD_ERR_ARG
     assert lib.mhd_cfl_dt(None, None, None) == mhd.MHD_ERR_ARG
+    assert lib.mhd_get_sums(None, None) == mhd.MHD_ERR_ARG
+    assert lib.mhd_step_info(None, None) == mhd.MHD_ERR_ARG
     lib.mhd_destroy(None)
 
 

@@ -29,3 +29,11 @@ def test_stored_counters_are_used_only_for_the_current_sources():
                 continue
             got = bench.measured_counters(key)
             assert (got is not None) == (ent.get("source_hash") == h)
+
+
+def test_cpu_baseline_helpers_time_the_oracle():
+    sys.path.insert(0, ROOT)
+    import bench
+    rate, wall, used, done = bench._oracle_rate("brio_wu", 400, 5, 1)
+    assert used == 1 and done == 5 and rate > 0 and wall > 0
+    assert isinstance(bench.cpu_model(), (str, type(None)))
