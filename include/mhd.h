@@ -213,6 +213,32 @@ mhd_status mhd_step_info(mhd_ctx *ctx, double out[11]);
  * the last syncing call. */
 mhd_status mhd_get_sums(mhd_ctx *ctx, double out[9]);
 
+/* mhd_step for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  No
+ * context: the config (validated as by mhd_init) is passed on each call,
+ * and the reduction partials, result words and non-physical flag live in
+ * a static device array of the library (about 1.4 MB per device, held until
+ * the process ends).  Nothing is allocated (no hipMalloc, hipFree or
+ * allocating library call); on the first call on a device (or at mhd_init
+ * on it) the library looks up that device's copy of the array.
+ * Same step, kernels and results as mhd_step (bit for bit), for SSP-RK2
+ * (time_order 2) without constrained transport (MHD_ERR_UNSUPPORTED
+ * otherwise: those need state-sized scratch) and flags = 0.  U1_out (the
+ * stage-1 state) is required; Un, U_next, U1_out are distinct device
+ * buffers of the config's dtype, caller owned.  Limit: the stage grid
+ * must fit the static partials (16384 workgroups: 512^3 needs 8192);
+ * larger grids get MHD_ERR_ARG before anything is enqueued.  info (host,
+ * 11 doubles) may be NULL: then the call is async and capturable (the flag
+ * is cleared by a kernel, not a memset); otherwise it syncs the stream and
+ * returns in info what mhd_step_info would (dt of the next step, c_h, FP64
+ * sums), or MHD_ERR_NONPHYSICAL if a kernel of this call saw a non-physical
+ * cell.  Every call on a device shares that device's array, which keeps the
+ * last call's contents: calls that overlap on one device (several streams
+ * or host threads) race and must be serialised by the caller.  Errors carry
+ * no text (there is no context for mhd_last_error). */
+mhd_status mhd_step_noalloc(const mhd_config *cfg, void *hip_stream, const void *Un, void *U_next,
+                            void *U1_out, double dt, double c_h, double damp, double info[11]);
+
 /* Adjoint of mhd_step (async).  The paper has no adjoint: this is the
  * transpose of the linearisation of the Runge-Kutta step of section 3.2
  * "Porting of gPLUTO" as mhd_step computes it (PLM, HLL or HLLD, GLM,

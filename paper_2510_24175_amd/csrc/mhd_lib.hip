@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -42,6 +43,9 @@ struct mhd_ctx {
     double dx[3] = {1, 1, 1};
     std::vector<hipEvent_t> events; // 4 per timed step
     int timed_cap = 0, timed_steps = 0;
+    // a transient context of mhd_step_noalloc: its buffers are the static
+    // scratch, each step first clears the flag, and errors keep no text
+    bool no_alloc = false;
     std::string err;
 };
 
@@ -51,13 +55,13 @@ constexpr int CFL_MAX_BLOCKS = 4096;
 
 mhd_status fail(mhd_ctx *ctx, mhd_status st, const char *msg)
 {
-    if (ctx) ctx->err = msg;
+    if (ctx && !ctx->no_alloc) ctx->err = msg;
     return st;
 }
 
 mhd_status fail_hip(mhd_ctx *ctx, const char *what, hipError_t e)
 {
-    if (ctx) ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+    if (ctx && !ctx->no_alloc) ctx->err = std::string(what) + ": " + hipGetErrorString(e);
     return MHD_ERR_HIP;
 }
 
@@ -134,6 +138,12 @@ mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, do
     constexpr int TY = tile_rows<T, LIM, NDIM>();
     const Launch L = plan_stage(ctx, TY);
     if (L.nblocks > ctx->part_cap) return fail(ctx, MHD_ERR_ARG, "grid too large for partials buffer");
+    if (ctx->no_alloc) {
+        // the static scratch keeps the last call's flag: this call reports
+        // only what its own kernels see
+        hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->flag);
+        HIP_TRY(ctx, hipGetLastError());
+    }
     StageArgs<T> a;
     a.part = ctx->part;
     a.flag = ctx->flag;
@@ -533,6 +543,46 @@ void destroy_events(mhd_ctx *ctx)
     ctx->timed_cap = ctx->timed_steps = 0;
 }
 
+// Static scratch of mhd_step_noalloc, one copy per device, held until the
+// process ends: the per-block partials of the last stage (NPART x
+// NOALLOC_MAX_BLOCKS doubles), the final reduction (NPART doubles) and the
+// non-physical flag.  Host code never uses the symbol itself (in host code
+// it is a stand-in, not a device address): the device address is looked up
+// once per device with hipGetSymbolAddress and kept in noalloc_ptr.
+constexpr int NOALLOC_MAX_BLOCKS = 16384;
+constexpr size_t NOALLOC_PART_BYTES = (size_t)NPART * NOALLOC_MAX_BLOCKS * sizeof(double);
+constexpr size_t NOALLOC_RESULT_OFF = NOALLOC_PART_BYTES;
+constexpr size_t NOALLOC_FLAG_OFF = NOALLOC_RESULT_OFF + 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_FLAG_OFF + 256;
+static_assert(NPART * sizeof(double) <= 256, "result words fit their slot");
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+void *noalloc_ptr[NOALLOC_MAX_DEVICES];  // device address of scratch per device
+bool noalloc_gfx950[NOALLOC_MAX_DEVICES];
+
+// Device address of the static scratch on the current device (looked up on
+// the first call per device, with that device current); MHD_ERR_NO_DEVICE
+// when the device is not a gfx950.
+mhd_status noalloc_scratch(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return MHD_ERR_NO_DEVICE;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MHD_ERR_NO_DEVICE;
+        noalloc_gfx950[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        if (!noalloc_gfx950[dev]) return MHD_ERR_NO_DEVICE;
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MHD_ERR_HIP;
+        noalloc_ptr[dev] = p;
+    }
+    if (!noalloc_gfx950[dev]) return MHD_ERR_NO_DEVICE;
+    *out = (unsigned char *)noalloc_ptr[dev];
+    return MHD_OK;
+}
+
 void free_ctx(mhd_ctx *ctx)
 {
     destroy_events(ctx);
@@ -620,6 +670,10 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MHD_ERR_NO_DEVICE;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MHD_ERR_NO_DEVICE;
+    // set-up of mhd_step_noalloc's static scratch on this device
+    unsigned char *noalloc_base = nullptr;
+    const mhd_status sst = noalloc_scratch(dev, &noalloc_base);
+    if (sst != MHD_OK) return sst;
 
     mhd_ctx *ctx = new (std::nothrow) mhd_ctx();
     if (!ctx) return MHD_ERR_HIP;
@@ -770,6 +824,64 @@ mhd_status mhd_get_sums(mhd_ctx *ctx, double out[9])
     mhd_status st = sync_results(ctx, ctx->result);
     if (st != MHD_OK) return st;
     for (int q = 0; q < NQ; ++q) out[q] = ctx->host_res[2 + q] * ctx->cell_volume;
+    return MHD_OK;
+}
+
+mhd_status mhd_step_noalloc(const mhd_config *cfg, void *hip_stream, const void *Un, void *U_next,
+                            void *U1_out, double dt, double c_h, double damp, double info[11])
+{
+    const char *why = "";
+    const mhd_status cst = check_config(cfg, why);
+    if (cst != MHD_OK) return cst;
+    if (cfg->flags != 0) return MHD_ERR_ARG;
+    if (cfg->time_order != 2 || cfg->ct) return MHD_ERR_UNSUPPORTED;
+    if (!Un || !U_next || !U1_out) return MHD_ERR_ARG;
+    if (Un == U_next || U1_out == Un || U1_out == U_next) return MHD_ERR_ARG;
+    if (!finite_pos(dt)) return MHD_ERR_ARG;
+    if (cfg->glm && !finite_pos(c_h)) return MHD_ERR_ARG;
+    if (!(damp > 0.0 && damp <= 1.0)) return MHD_ERR_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MHD_ERR_NO_DEVICE;
+    unsigned char *base = nullptr;
+    const mhd_status sst = noalloc_scratch(dev, &base);
+    if (sst != MHD_OK) return sst;
+
+    // a transient context over the static scratch (no member allocates:
+    // the event list stays empty and errors keep no text)
+    mhd_ctx c;
+    c.no_alloc = true;
+    c.cfg = *cfg;
+    c.stream = (hipStream_t)hip_stream;
+    c.device = dev;
+    c.ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        c.n[d] = cfg->n[d];
+        c.ncell *= cfg->n[d];
+        c.dx[d] = d < cfg->ndim ? (cfg->hi[d] - cfg->lo[d]) / (double)cfg->n[d] : 1.0;
+        if (d < cfg->ndim) c.cell_volume *= c.dx[d];
+    }
+    c.elem = cfg->dtype == MHD_F32 ? 4 : 8;
+    c.part = (double *)base;
+    c.part_cap = NOALLOC_MAX_BLOCKS;
+    c.result = (double *)(base + NOALLOC_RESULT_OFF);
+    c.flag = (int *)(base + NOALLOC_FLAG_OFF);
+    // launch_step refuses a stage grid beyond NOALLOC_MAX_BLOCKS with
+    // MHD_ERR_ARG before it enqueues anything
+    const mhd_status st = with_scheme(&c, [&](auto sch) {
+        using S = decltype(sch);
+        return launch_step_nd<typename S::T, S::SOLVER, S::LIM>(&c, Un, U_next, U1_out, dt, c_h, damp);
+    });
+    if (st != MHD_OK || !info) return st;
+    double res[NPART];
+    int flag = 0;
+    if (hipMemcpyAsync(res, c.result, sizeof res, hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+        hipMemcpyAsync(&flag, c.flag, sizeof flag, hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+        hipStreamSynchronize(c.stream) != hipSuccess)
+        return MHD_ERR_HIP;
+    if (flag) return MHD_ERR_NONPHYSICAL;
+    info[0] = cfg->cfl / res[0];
+    info[1] = res[1];
+    for (int q = 0; q < NQ; ++q) info[2 + q] = res[2 + q] * c.cell_volume;
     return MHD_OK;
 }
 

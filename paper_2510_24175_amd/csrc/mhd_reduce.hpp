@@ -42,6 +42,10 @@ cfl_kernel(const T *__restrict__ U, long long ncell, double gamma, double idx0, 
     }
 }
 
+// Clears the non-physical flag (a kernel rather than a memset, so that a
+// caller may capture it in a HIP graph).
+__global__ void clear_flag_kernel(int *flag) { *flag = 0; }
+
 // One workgroup folds nblocks partials into out[NPART] in a fixed order:
 // each thread runs over a strided subset sequentially, then a fixed tree.
 __global__ void __launch_bounds__(RED_THREADS)

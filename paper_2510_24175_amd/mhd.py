@@ -81,6 +81,8 @@ def load_library():
         "mhd_step": ([vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], ctypes.c_int),
         "mhd_step_info": ([vp, dp], ctypes.c_int),
         "mhd_get_sums": ([vp, dp], ctypes.c_int),
+        "mhd_step_noalloc": ([ctypes.POINTER(mhd_config), vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_double, dp], ctypes.c_int),
         "mhd_step_adjoint": ([vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
                              ctypes.c_int),
         "mhd_prim_to_cons_adjoint": ([vp, vp, vp, vp], ctypes.c_int),
@@ -117,6 +119,27 @@ def make_config(setup, dtype="f32", adjoint=False):
     c.time_order = int(setup.get("time_order", 2))
     c.ct = 1 if setup.get("ct", False) else 0
     return c
+
+
+def step_noalloc(setup, dtype, Un, U_next, U1_out, dt, ch, damp, info=True, stream=None):
+    """mhd_step_noalloc: one SSP-RK2 step without a context and without any
+    allocation (static device scratch of the library).  Returns (dt_next,
+    c_h_next, sums[9]) when info is true (syncs), else None (async)."""
+    lib = load_library()
+    cfg = make_config(setup, dtype)
+    shape = (9, int(setup["n"][2]), int(setup["n"][1]), int(setup["n"][0]))
+    for name, x in (("Un", Un), ("U_next", U_next), ("U1_out", U1_out)):
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or not x.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous device tensor")
+        if tuple(x.shape) != shape or x.dtype != TORCH_DTYPE[dtype]:
+            raise ValueError(f"{name}: expected {shape} {TORCH_DTYPE[dtype]}, got {tuple(x.shape)} {x.dtype}")
+    out = (ctypes.c_double * 11)() if info else None
+    ptrs = [ctypes.c_void_p(x.data_ptr()) for x in (Un, U_next, U1_out)]
+    st = lib.mhd_step_noalloc(ctypes.byref(cfg), _stream_handle(stream), *ptrs, float(dt), float(ch),
+                              float(damp), out)
+    if st != MHD_OK:
+        raise MHDError(st, "mhd_step_noalloc: " + lib.mhd_status_string(st).decode())
+    return (out[0], out[1], list(out[2:11])) if info else None
 
 
 def _stream_handle(stream=None):
