@@ -19,8 +19,10 @@
  *     scheme of the paper's benchmark runs (section "Results for gPLUTO");
  *   - GLM: Dedner et al. (2002) mixed GLM, exact (B_n, psi) interface
  *     solve, psi damped by exp(-alpha c_h dt / dh_min) once per step;
- *   - Riemann: HLL (Harten, Lax & van Leer 1983) or HLLD (Miyoshi & Kusano
- *     2005) with Davis wave-speed bounds;
+ *   - Riemann: HLL (Harten, Lax & van Leer 1983) with Davis wave-speed
+ *     bounds, or HLLD (Miyoshi & Kusano 2005) with outer speeds
+ *     min(u_L, u_R) - max(c_fL, c_fR) and max(u_L, u_R) + max(c_fL, c_fR),
+ *     which keep its rotational waves inside the fan;
  *   - time: SSP-RK2 or SSP-RK3 (Shu & Osher 1988; RK3 is the benchmark
  *     integrator of the paper), dt and c_h fixed for the step;
  *   - CFL: dt = C / max_{cells,d} (|v_d| + c_f,d)/dx_d and

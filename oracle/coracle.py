@@ -51,7 +51,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        path = _build.build(force=False)
+        # MHD_ORACLE_LIB names another build of the same source (for example
+        # one compiled with sanitizers); otherwise the in-tree build
+        path = os.environ.get("MHD_ORACLE_LIB") or _build.build(force=False)
         L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         cp = ctypes.POINTER(_Cfg)

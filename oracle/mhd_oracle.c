@@ -28,8 +28,10 @@
  *              eps = 1e-40.
  *   GLM      : Dedner et al. (2002) mixed GLM: the (B_n, psi) 2x2 system is
  *              solved exactly at each interface before the MHD solver.
- *   Riemann  : HLL (Harten, Lax & van Leer 1983) or HLLD (Miyoshi & Kusano
- *              2005) with Davis wave-speed bounds u -/+ c_f.
+ *   Riemann  : HLL (Harten, Lax & van Leer 1983) with Davis wave-speed
+ *              bounds min/max of u -/+ c_f, or HLLD (Miyoshi & Kusano 2005)
+ *              with outer speeds min(u_L, u_R) - max(c_fL, c_fR) and
+ *              max(u_L, u_R) + max(c_fL, c_fR).
  *   RHS      : L = -sum_d (F_{i+1/2} - F_{i-1/2}) / dx_d, d = x, y, z.
  *   RK2      : SSP-RK2 (Shu & Osher 1988): U1 = Un + dt L(Un);
  *              Un+1 = (Un + U1 + dt L(U1)) / 2, dt and c_h fixed per step.
@@ -334,8 +336,13 @@ static void hlld_build_fan(const double *qL, const double *qR, double gamma, hll
     double bn = qL[5]; /* equal on both sides after the GLM step */
     double cL = fast_speed_rot(qL, gamma), cR = fast_speed_rot(qR, gamma);
     double uL = qL[1], uR = qR[1];
-    double sL = fmin(uL - cL, uR - cR);
-    double sR = fmax(uL + cL, uR + cR);
+    /* outer speeds: the slower (faster) normal velocity minus (plus) the
+     * larger fast speed, a bound at least as wide as Davis's that keeps the
+     * rotational waves S*_a inside [S_L, S_R] (D_a > 0) in the states where
+     * Davis's bound lets D_a cross zero and the star states diverge */
+    double cm = fmax(cL, cR);
+    double sL = fmin(uL, uR) - cm;
+    double sR = fmax(uL, uR) + cm;
     double ptL = qL[4] + 0.5 * (qL[5] * qL[5] + qL[6] * qL[6] + qL[7] * qL[7]);
     double ptR = qR[4] + 0.5 * (qR[5] * qR[5] + qR[6] * qR[6] + qR[7] * qR[7]);
     double mL = (sL - uL) * qL[0], mR = (sR - uR) * qR[0];

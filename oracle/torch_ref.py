@@ -9,7 +9,9 @@ at exact ties the choices are: minmod takes the left difference when
 |a| = |b| != 0; where an argument is exactly zero (uniform fields,
 symmetric samples) the derivative is the one a central difference sees
 (see limited_slope); the MC limiter prefers 2*minmod over the central
-difference; the Davis minimum/maximum take the left state;
+difference; the minima and maxima of the outer wave speeds (Davis's for
+HLL; min/max of the normal velocities and the larger fast speed for HLLD)
+take the left state;
 sign(B_n = 0) = +1.
 Denominators of branches that are not taken are replaced by 1 so that they
 cannot poison gradients.
@@ -135,10 +137,10 @@ def hlld(qL, qR, gamma):
     cL = fast_speed(qL[0], qL[4], bsqL, bn * bn, gamma)
     cR = fast_speed(qR[0], qR[4], bsqR, bn * bn, gamma)
     uL, uR = qL[1], qR[1]
-    xl, xr = uL - cL, uR - cR
-    sL = torch.where(xl <= xr, xl, xr)
-    yl, yr = uL + cL, uR + cR
-    sR = torch.where(yl >= yr, yl, yr)
+    # outer speeds min(u_L, u_R) - max(c_L, c_R), max(u_L, u_R) + max(c_L, c_R)
+    cm = torch.where(cL >= cR, cL, cR)
+    sL = torch.where(uL <= uR, uL, uR) - cm
+    sR = torch.where(uL >= uR, uL, uR) + cm
     mL = (sL - uL) * qL[0]
     mR = (sR - uR) * qR[0]
     sM = (mR * uR - mL * uL - ptR + ptL) / (mR - mL)

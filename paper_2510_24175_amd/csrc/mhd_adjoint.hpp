@@ -264,9 +264,10 @@ __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R,
     // ---- forward ----
     T sdL, sdR;
     const T cL = fast_fwd(L, ph, sdL), cR = fast_fwd(R, ph, sdR);
-    const T xL = L.u - cL, xR = R.u - cR, yL = L.u + cL, yR = R.u + cR;
-    const bool selx = xL <= xR, sely = yL >= yR;
-    const T sL = selx ? xL : xR, sR = sely ? yL : yR;
+    // outer speeds as hlld_flux; ties pick the left state
+    const bool uminl = L.u <= R.u, umaxl = L.u >= R.u, cmaxl = cL >= cR;
+    const T cm = cmaxl ? cL : cR;
+    const T sL = (uminl ? L.u : R.u) - cm, sR = (umaxl ? L.u : R.u) + cm;
     const T mL = (sL - L.u) * L.rho, mR = (sR - R.u) * R.rho;
     const T idm = Num<T>::rcp(mR - mL);
     const T nsM = mR * R.u - mL * L.u - R.pt + L.pt;
@@ -442,8 +443,9 @@ __device__ __forceinline__ void hlld_vjp(const RState<T> &L, const RState<T> &R,
     Rb.u -= mRb * R.rho;
     Rb.rho += mRb * (sR - R.u);
     T cLb = 0, cRb = 0;
-    if (selx) { Lb.u += sLb; cLb -= sLb; } else { Rb.u += sLb; cRb -= sLb; }
-    if (sely) { Lb.u += sRb; cLb += sRb; } else { Rb.u += sRb; cRb += sRb; }
+    if (uminl) Lb.u += sLb; else Rb.u += sLb;
+    if (umaxl) Lb.u += sRb; else Rb.u += sRb;
+    if (cmaxl) cLb += sRb - sLb; else cRb += sRb - sLb;
     // flux, conserved vector and energy of the picked side
     flux_rev(S, Fb, ub, xb, xd);
     energy_rev(S, ph, xd.E, xd.vb, xb);

@@ -326,16 +326,21 @@ __device__ __forceinline__ void hlld_star_energy(const RState<T> &s, const Star<
     Es = (o.su * s.E - s.pt * s.u + pts * sM + s.bn * (s.vb - vbs)) * o.isd;
 }
 
-// HLLD flux (Miyoshi & Kusano 2005) with Davis outer speeds.  L and R need
+// HLLD flux (Miyoshi & Kusano 2005), outer speeds min(u_L, u_R) - max(c_fL,
+// c_fR) and max(u_L, u_R) + max(c_fL, c_fR).  L and R need
 // irho, bsq and pt (rstate_prepare); E and v.B are formed for the side the
 // flux is taken from.
 template <typename T>
 __device__ __forceinline__ void hlld_flux(const RState<T> &L, const RState<T> &R,
                                           const Phys<T> &ph, T *F)
 {
+    // outer speeds: the slower (faster) normal velocity minus (plus) the
+    // larger fast speed (at least as wide as Davis's bounds; keeps the
+    // rotational waves inside the fan where Davis's bounds let D cross zero)
     const T cL = rstate_fast(L, ph), cR = rstate_fast(R, ph);
-    const T sL = Num<T>::min(L.u - cL, R.u - cR);
-    const T sR = Num<T>::max(L.u + cL, R.u + cR);
+    const T cm = Num<T>::max(cL, cR);
+    const T sL = Num<T>::min(L.u, R.u) - cm;
+    const T sR = Num<T>::max(L.u, R.u) + cm;
     const T mL = (sL - L.u) * L.rho, mR = (sR - R.u) * R.rho;
     const T idm = Num<T>::rcp(mR - mL);
     const T sM = (mR * R.u - mL * L.u - R.pt + L.pt) * idm;

@@ -24,7 +24,8 @@ of those runs are not printed, so these are synthetic stand-ins):
                    travelling solution), 1D/2D/3D, any direction;
                    ``cpa_wave_3d`` along the cube diagonal (the paper's
                    second benchmark problem).
-* ``sod``, ``uniform``, ``stationary_contact``: closed-form test states.
+* ``sod``, ``uniform``, ``stationary_contact``, ``switch_on_tube``:
+                   closed-form test states.
 """
 import math
 
@@ -105,6 +106,26 @@ def stationary_contact(n=64, riemann="hlld"):
     V[5] = 1.0
     V[6] = 0.5
     V[7] = 0.3
+    return s, V
+
+
+def switch_on_tube(n=400, riemann="hlld", t_end=0.08):
+    """1D tube with a strong normal field and no tangential field on the
+    left: gamma = 5/3, B_x = 3, left (rho, p, B_y) = (3, 3, 0), right
+    (1, 1, 1), v = 0, B_z = 0; outflow, CFL 0.4.  On the left the Alfven
+    speed exceeds the sound speed and the tangential field is zero, so the
+    fast and Alfven speeds coincide there: the degenerate case of the HLLD
+    star states (keep v_t and B_t) at every interface of that region until
+    the waves from the jump switch the tangential field on."""
+    s = make_setup("switch_on", 1, (n,), gamma=5.0 / 3.0, cfl=0.4, riemann=riemann, bc=OUTFLOW_X,
+                   t_end=t_end)
+    x = cell_centres(s)[0]
+    V = _empty(s)
+    left = x < 0.5
+    V[0, 0, 0] = np.where(left, 3.0, 1.0)
+    V[4, 0, 0] = np.where(left, 3.0, 1.0)
+    V[5] = 3.0
+    V[6, 0, 0] = np.where(left, 0.0, 1.0)
     return s, V
 
 
@@ -271,14 +292,12 @@ def smooth_direction(n, seed, kmax=4):
 
 # ------------------------------------------------------- Orszag-Tang -------
 
-def orszag_tang(n=1024, seed=3, riemann="hlld", cfl=0.3, t_end=0.5):
+def orszag_tang(n=1024, seed=3, riemann="hlld", cfl=0.4, t_end=0.5):
     """2D periodic Orszag & Tang (1979)-type vortex on [0,1]^2:
     rho = 25/(36 pi), p = 5/(12 pi), gamma = 5/3,
     v = (-a1 sin 2pi y, a2 sin 2pi x), B = B0 (-a3 sin 2pi y, a4 sin 4pi x),
     B0 = 1/sqrt(4 pi), a_i = 1 + 0.05 u_i with u_i ~ U(-1, 1) from the seed.
-    Courant number 0.3: with 0.4 this scheme (PLM minmod + HLLD + GLM, SSP-RK2,
-    no floors) produces a non-positive pressure before t = 0.5 at 512^2 and
-    1024^2."""
+    Courant number 0.4 (the setup names none)."""
     if isinstance(n, int):
         n = (n, n)
     s = make_setup("orszag_tang", 2, n, gamma=5.0 / 3.0, cfl=cfl, riemann=riemann, t_end=t_end)

@@ -10,9 +10,8 @@
   (128^3, 200 steps, checkpoints every 20, 8 smooth directions, eps 1e-3)
   and at 24^3;
 * the same gradient against the reference gradient of the PyTorch step at
-  32^3 (40 steps; all 200 steps when MHD_FULL_CHECKS=1).
+  32^3 (the workload's 200 steps, checkpoints every 20).
 """
-import os
 import sys
 
 import numpy as np
@@ -152,7 +151,7 @@ def test_rollout_gradient_vs_reference_gradient():
     from paper_2510_24175_amd.adjoint import Rollout, kinetic_energy
     from paper_2510_24175_amd.mhd import Context
     n = 32
-    nsteps = 200 if os.environ.get("MHD_FULL_CHECKS") == "1" else 40
+    nsteps = 200
     _say(f"[gpu-adjoint] rollout vs reference {n}^3 {nsteps} steps")
     s, V = W.turbulence(n)
     o = C.Oracle(s)

@@ -1,30 +1,40 @@
-"""GPU path at the workloads' full sizes, in the launch configuration the
+"""GPU path at the workloads' full sizes, in the launch configurations the
 benchmark uses.
 
-* 512^3 turbulence, FP32: one step compared cell by cell at sampled cells
-  (corners, tile and z-chunk boundaries, random) with the FP64 oracle run on
-  an 11^3 periodic window around each cell (a step at a cell depends only on
-  cells within 4 along each axis; the window reproduces the full-grid value,
-  pinned in the oracle tests); dt and c_h from the oracle's full-grid CFL;
-  the GPU's own CFL against it; FP64 conservation sums over two steps.
-* 128^3 turbulence, FP64: full-grid comparison after 10 steps (100 steps
-  with MHD_FULL_CHECKS=1).
+* 512^3 turbulence, FP32 and FP64 (the benchmark's main and FP64 legs): one
+  step compared cell by cell at sampled cells (corners, tile and z-chunk
+  boundaries, random) with the FP64 oracle run on an 11^3 periodic window
+  around each cell (a step at a cell depends only on cells within 4 along
+  each axis; the window reproduces the full-grid value, pinned in the
+  oracle tests); dt and c_h from the oracle's full-grid CFL; the GPU's own
+  CFL against it; FP64 conservation sums over two steps.
+* 512^3 turbulence, FP32, 50 steps (the precision workload): against the
+  GPU FP64 path on the same grid replaying the same dt history (a labelled
+  proxy for the FP64 oracle at this size; the FP64 path is tied to the
+  oracle by the 128^3 full-grid test and the sampled 512^3 step): relative
+  L1 per component <= 1e-5, and the FP64 sums of both runs against the
+  oracle's sums of the initial state (conserved on a periodic grid).
+* 512^3 adjoint step: FP64 lambda_n at sampled cells against the FP64
+  PyTorch reference gradient on a 19^3 window around each cell; FP32 (the
+  benchmark's adjoint leg) by directional derivatives along smooth
+  directions against central differences of the GPU FP64 forward.
+* 128^3 turbulence, FP64: full-grid comparison with the oracle after 100
+  steps.
 * 1024^2 Orszag-Tang: 10 FP32 steps against the oracle on the full grid;
-  a run to t = 0.4 (Courant number 0.15) in FP64 and FP32 checked for
-  conservation and for the 180-degree rotation symmetry of the setup.
+  the run to t = 0.5 in FP64 and FP32 checked for conservation and for the
+  180-degree rotation symmetry of the setup.
 """
-import os
-
 import numpy as np
 import pytest
 import torch
 
 from oracle import coracle as C
+from oracle import torch_ref as R
 from paper_2510_24175_amd import workloads as W
-from tests.helpers import rel_l1
+from tests.helpers import rel_l1, rel_l1_own
 
 pytestmark = pytest.mark.gpu
-FULL = os.environ.get("MHD_FULL_CHECKS") == "1"
+N512 = 512
 
 
 def _say(msg):
@@ -39,58 +49,231 @@ def _sample_cells(n, rng, count=40):
     return [(k, j, i) for (i, j, k) in cells]
 
 
-def test_turbulence_512_fp32_one_step_sampled():
-    from paper_2510_24175_amd.mhd import Context
-    n = 512
-    _say("[gpu-fullsize] turbulence 512^3 FP32, generating fields")
-    s, V = W.turbulence(n)
+@pytest.fixture(scope="module")
+def turb512():
+    """The 512^3 turbulence fields, their oracle conserved state, CFL and
+    sums (host, FP64)."""
+    _say("[gpu-fullsize] turbulence 512^3: generating fields")
+    s, V = W.turbulence(N512)
     o = C.Oracle(s)
     Uo = o.prim_to_cons(V)
     dt, ch = o.cfl(Uo)
-    dmp = o.damp(dt, ch)
     _say(f"    oracle CFL dt={dt:.6e} c_h={ch:.6e}")
-    ctx = Context(s, "f32")
+    return s, V, o, Uo, dt, ch, o.sums(Uo)
+
+
+def _window(Uo, k, j, i, r, n):
+    idx = np.ix_(range(Uo.shape[0]), [(k + a) % n for a in range(-r, r + 1)],
+                 [(j + a) % n for a in range(-r, r + 1)], [(i + a) % n for a in range(-r, r + 1)])
+    return Uo[idx]
+
+
+def _window_setup(s, r, n):
+    return W.make_setup("window", 3, (2 * r + 1,) * 3, gamma=s["gamma"], cfl=s["cfl"],
+                        riemann=s["riemann"], bc=(("outflow", "outflow"),) * 3,
+                        hi=tuple((2 * r + 1) / n for _ in range(3)))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_turbulence_512_one_step_sampled(turb512, dtype):
+    from paper_2510_24175_amd.mhd import Context
+    s, V, o, Uo, dt, ch, _ = turb512
+    n = N512
+    dmp = o.damp(dt, ch)
+    _say(f"[gpu-fullsize] turbulence 512^3 {dtype}: one step at sampled cells")
+    ctx = Context(s, dtype)
     Ug = ctx.prim_to_cons(torch.from_numpy(V).cuda())
-    del V
     dtg, chg = ctx.cfl_dt(Ug)
-    assert abs(dtg / dt - 1) < 1e-6 and abs(chg / ch - 1) < 1e-6, (dtg, dt, chg, ch)
+    tol_cfl = 1e-6 if dtype == "f32" else 1e-14
+    assert abs(dtg / dt - 1) < tol_cfl and abs(chg / ch - 1) < tol_cfl, (dtg, dt, chg, ch)
     out = torch.empty_like(Ug)
     ctx.step(Ug, out, dt, ch, dmp)
-    _, _, sums1 = ctx.step_info()
+    sums1 = ctx.get_sums()
     out2 = torch.empty_like(Ug)
     dt2, ch2, _ = ctx.step_info()
     ctx.step(out, out2, dt2, ch2, ctx.damp(dt2, ch2))
-    _, _, sums2 = ctx.step_info()
+    sums2 = ctx.get_sums()
     torch.cuda.synchronize()
-    # periodic: rho, m, E, B conserved up to the FP32 rounding of the stored state
+    del out2, Ug
+    # periodic: rho, m, E, B conserved up to the rounding of the stored state
     scale = np.array([np.abs(Uo[q]).sum() for q in range(9)]) * o.cell_volume
     dsum = np.abs(np.array(sums2) - np.array(sums1))[:8] / scale[:8]
-    _say(f"    conservation over one FP32 step (FP64 sums): {dsum.max():.2e}")
-    assert dsum.max() <= 1e-6
+    _say(f"    conservation over one step (FP64 sums): {dsum.max():.2e}")
+    assert dsum.max() <= (1e-6 if dtype == "f32" else 1e-13)
     # sampled cells against the oracle on an 11^3 window
     r = 5
-    sub = W.make_setup("window", 3, (2 * r + 1,) * 3, gamma=s["gamma"], cfl=s["cfl"],
-                       riemann=s["riemann"], bc=(("outflow", "outflow"),) * 3,
-                       hi=tuple((2 * r + 1) / n for _ in range(3)))
-    ow = C.Oracle(sub)
+    ow = C.Oracle(_window_setup(s, r, n))
     rng = np.random.default_rng(9)
     comp_scale = np.maximum(np.abs(Uo).max(axis=(1, 2, 3)), 1e-2)
+    tol = 1e-5 if dtype == "f32" else 1e-10
     worst = 0.0
     for (k, j, i) in _sample_cells(n, rng):
-        idx = np.ix_(range(9), [(k + a) % n for a in range(-r, r + 1)],
-                     [(j + a) % n for a in range(-r, r + 1)], [(i + a) % n for a in range(-r, r + 1)])
-        ref = ow.step(Uo[idx], dt, ch, dmp)[:, r, r, r]
+        ref = ow.step(_window(Uo, k, j, i, r, n), dt, ch, dmp)[:, r, r, r]
         got = out[:, k, j, i].double().cpu().numpy()
         err = (np.abs(got - ref) / comp_scale).max()
         worst = max(worst, err)
-        assert err <= 1e-5, ((k, j, i), got, ref)
+        assert err <= tol, ((k, j, i), got, ref)
     _say(f"    worst sampled-cell error (per-component scaled): {worst:.2e}")
+    ctx.close()
+    del out
+    torch.cuda.empty_cache()
+
+
+def test_turbulence_512_fp32_50_steps_against_fp64(turb512):
+    from paper_2510_24175_amd.mhd import Context
+    from paper_2510_24175_amd.rollout import advance
+    s, V, o, Uo, _, _, sums0 = turb512
+    _say("[gpu-fullsize] turbulence 512^3: 50 FP32 steps against the FP64 path (same dt history)")
+    Vd = torch.from_numpy(V).cuda()
+    c32 = Context(s, "f32")
+    U32, t32, hist = advance(c32, c32.prim_to_cons(Vd), nsteps=50)
+    s32 = c32.get_sums()
+    c64 = Context(s, "f64")
+    U64, t64, _ = advance(c64, c64.prim_to_cons(Vd), history=hist)
+    s64 = c64.get_sums()
+    del Vd
+    torch.cuda.synchronize()
+    num = np.array([float((U32[q].double() - U64[q]).abs().sum()) for q in range(9)])
+    den = np.array([float(U64[q].abs().sum()) for q in range(9)])
+    own = num / den
+    # the gate as in the parity tests: m and B components against a tenth of
+    # their vector's sum at least; psi against c_h sum|B|
+    gate = own.copy()
+    for q in range(8):
+        if q in (1, 2, 3, 5, 6, 7):
+            v0 = 1 if q < 4 else 5
+            gate[q] = num[q] / max(den[q], 0.1 * den[v0:v0 + 3].sum())
+    gate[8] = num[8] / (hist[-1][1] * den[5:8].sum())
+    _say(f"    t = {t32:.6e}; rel L1 per component (gate) {np.array2string(gate, precision=2)}")
+    _say(f"    own-size rel L1                        {np.array2string(own, precision=2)}")
+    assert gate.max() <= 1e-5, gate
+    # full-grid invariants: both runs' FP64 sums against the oracle's sums
+    # of the initial state (periodic: rho, m, E, B conserved)
+    scale = np.array([np.abs(Uo[q]).sum() for q in range(9)]) * o.cell_volume
+    d32 = (np.abs(np.array(s32) - sums0) / scale)[:8]
+    d64 = (np.abs(np.array(s64) - sums0) / scale)[:8]
+    _say(f"    sums vs oracle's initial sums: FP32 {d32.max():.2e}, FP64 {d64.max():.2e}")
+    assert d32.max() <= 1e-5 and d64.max() <= 1e-12
+    c32.close()
+    c64.close()
+    del U32, U64
+    torch.cuda.empty_cache()
+
+
+def _generic512(V):
+    """A generic state from the 512^3 fields (device, FP64 primitives): at
+    the turbulence start rho and p are uniform, p only up to the rounding of
+    E - |m|^2/2rho - |B|^2/2, so the limiter branches of p follow rounding
+    noise that differs between two implementations; here no component is
+    uniform."""
+    Vg = torch.from_numpy(V).cuda()
+    Vg[0] = 1.0 + 0.1 * Vg[2]
+    Vg[4] = 1.0 + 0.1 * Vg[3]
+    Vg[8] = 0.03 * Vg[1]
+    return Vg
+
+
+def test_adjoint_512_fp64_sampled_against_reference(turb512):
+    """lambda_n = dJ/dU_n of one step at 512^3 in the FP64 launch
+    configuration, at sampled cells, against the FP64 PyTorch reference on
+    a 19^3 outflow window (lambda_n at a cell depends on lambda' within 4
+    cells and on U_n within 8; the window's boundary treatment reaches 4
+    cells in, so its centre is exact)."""
+    from paper_2510_24175_amd.mhd import Context
+    s, V, o, _, _, _, _ = turb512
+    n = N512
+    _say("[gpu-fullsize] adjoint 512^3 f64: sampled cells")
+    ctx = Context(s, "f64", adjoint=True)
+    Vg = _generic512(V)
+    Ug = ctx.prim_to_cons(Vg)
+    del Vg
+    dt, ch = ctx.cfl_dt(Ug)
+    dmp = ctx.damp(dt, ch)
+    gen = torch.Generator(device="cuda").manual_seed(21)
+    lam = torch.randn(Ug.shape, dtype=torch.float64, device="cuda", generator=gen)
+    lamn = torch.empty_like(lam)
+    ctx.step_adjoint(Ug, None, lam, lamn, dt, ch, dmp)
+    torch.cuda.synchronize()
+    r = 9
+    ws = _window_setup(s, r, n)
+    rng = np.random.default_rng(10)
+    got, ref = [], []
+    for (k, j, i) in _sample_cells(n, rng, count=16):
+        kk, jj, ii = (torch.tensor([(c + a) % n for a in range(-r, r + 1)], device="cuda") for c in (k, j, i))
+        Uw = Ug[:, kk][:, :, jj][:, :, :, ii].cpu()
+        lw = lam[:, kk][:, :, jj][:, :, :, ii].cpu()
+        Ut = Uw.clone().requires_grad_(True)
+        J = (lw * R.step(Ut, ws, dt, ch, dmp)).sum()
+        (g,) = torch.autograd.grad(J, Ut)
+        ref.append(g[:, r, r, r].numpy())
+        got.append(lamn[:, k, j, i].cpu().numpy())
+    got, ref = np.array(got), np.array(ref)
+    err = (np.abs(got - ref) / np.abs(ref).max(axis=0)).max()
+    _say(f"    worst sampled-cell error (per-component scaled): {err:.2e}")
+    assert err <= 1e-10, err
+    ctx.close()
+    del Ug, lam, lamn
+    torch.cuda.empty_cache()
+
+
+def test_adjoint_512_fp32_directional_derivatives(turb512):
+    """The FP32 adjoint step at 512^3 in its launch configuration (8-row
+    tiles, 64-plane z chunks): <lambda_n, dU> along smooth directions dU
+    against central differences of J(U) = <lambda', step(U)> with the GPU
+    FP64 forward (pinned to the oracle), dt, c_h and the decay factor fixed.
+    Pointwise the FP32 adjoint is the derivative of the FP32 step's own
+    branches: where two limiter arguments are within FP32 rounding of each
+    other (smooth regions at this resolution, |a - b| ~ dx |a|) it may take
+    the other branch than an FP64 evaluation, an O(1) change of a few
+    cells' lambda_n, which a smooth direction averages out."""
+    from paper_2510_24175_amd.mhd import Context
+    s, V, o, _, _, _, _ = turb512
+    n = N512
+    _say("[gpu-fullsize] adjoint 512^3 f32: directional derivatives vs FP64 central differences")
+    Vg = _generic512(V)
+    c64 = Context(s, "f64")
+    U64 = c64.prim_to_cons(Vg)
+    c32 = Context(s, "f32", adjoint=True)
+    U32 = c32.prim_to_cons(Vg)
+    del Vg
+    dt, ch = c64.cfl_dt(U64)
+    dmp = c64.damp(dt, ch)
+    # a smooth lambda' (a smooth functional): the directional derivative is
+    # then a coherent sum, against which branch flips at a few cells are
+    # noise of relative size ~ sqrt(flips) / N
+    f = torch.from_numpy(W.smooth_direction(n, 102)).cuda()
+    lam = torch.stack([f[q % 3] for q in range(9)])
+    del f
+    lamn = torch.empty_like(lam)
+    c32.step_adjoint(U32, None, lam, lamn, dt, ch, dmp)
+    rms = U64.square().mean(dim=(1, 2, 3)).sqrt()
+    out = torch.empty_like(U64)
+
+    def J(U):
+        c64.step(U, out, dt, ch, dmp)
+        return float((lam * out).sum())
+
+    eps = 1e-6
+    for seed in (100, 101):
+        f = torch.from_numpy(W.smooth_direction(n, seed)).cuda()
+        dU = torch.stack([f[q % 3] * rms[q] for q in range(9)])
+        del f
+        fd = (J(U64 + eps * dU) - J(U64 - eps * dU)) / (2 * eps)
+        ad = float((lamn * dU).sum())
+        rel = abs(fd - ad) / abs(fd)
+        _say(f"    direction {seed}: fd {fd:.10e} adjoint {ad:.10e} rel {rel:.2e}")
+        assert rel <= 1e-4, (fd, ad)
+        del dU
+    c32.close()
+    c64.close()
+    del U64, U32, lam, lamn, out
+    torch.cuda.empty_cache()
 
 
 def test_turbulence_128_fp64_full_grid():
     from paper_2510_24175_amd.mhd import Context
     from paper_2510_24175_amd.rollout import advance
-    nsteps = 100 if FULL else 10
+    nsteps = 100
     _say(f"[gpu-fullsize] turbulence 128^3 FP64, {nsteps} steps, full grid")
     s, V = W.turbulence(128)
     ctx = Context(s, "f64")
@@ -100,7 +283,10 @@ def test_turbulence_128_fp64_full_grid():
     Uo, _, ho = o.run(o.prim_to_cons(V), nsteps=nsteps)
     err = rel_l1(Ug, Uo, ch=ho[-1][1])
     _say(f"    rel L1 per component {np.array2string(err, precision=2)}")
+    _say(f"    own-size rel L1      {np.array2string(rel_l1_own(Ug, Uo), precision=2)}")
     assert err.max() <= 1e-10
+    dg, do = np.array([h[0] for h in hg]), np.array([h[0] for h in ho])
+    assert (np.abs(dg - do) / do).max() <= 1e-12
 
 
 def _rot_asym(U):
@@ -124,30 +310,20 @@ def test_orszag_tang_1024():
     assert err.max() <= 1e-5
     o_sums0 = o.sums(o.prim_to_cons(V))
     scale = np.array([np.abs(Uo[q]).sum() for q in range(9)]) * o.cell_volume
-    # Without floors this scheme (PLM minmod + HLLD + GLM, SSP-RK2) loses
-    # pressure positivity on this setup at 1024^2 before t = 0.5 for Courant
-    # numbers 0.2 - 0.3 in FP64 (the FP64 oracle at 0.3 fails at t = 0.398, as
-    # the GPU path does).  At 0.15 the run is on the edge near t = 0.44: the
-    # FP64 oracle reaches t = 0.5, while two GPU builds whose steps agree to
-    # 3e-16 on the same input (the HLLD flux written with and without terms
-    # that are exactly zero) follow trajectories that agree to 1e-15 through
-    # step 6500 and then part, one reaching t = 0.5 and the other stopping at
-    # t = 0.4386.  The long run therefore ends at t = 0.4 (Courant number 0.15).  The point symmetry
-    # holds up to rounding differences that the shock interactions amplify:
-    # the FP64 oracle's own asymmetry on this setup at 512^2 (4372 steps) is
-    # 4.3e-6, and the GPU FP64 state there differs from the oracle's by 6e-6
-    # (rel L1).  Conservation: FP64 to rounding (3e-16 measured); the FP32
-    # state is rounded at every cell update, and over the 8795 steps to
-    # t = 0.5 the FP64 sums of the FP32 states drifted by 2.3e-6 of sum |q|
-    # (measured), so 1e-5.
-    s_long = dict(s, cfl=0.15)
-    t_long = 0.4
+    # The run to t = 0.5 at the setup's Courant number 0.4 (3298 steps).  The
+    # point symmetry holds up to rounding differences that the shock
+    # interactions amplify: the FP64 oracle's own asymmetry on this setup at
+    # 512^2 is of the order of 1e-6, and FP32 rounding of every cell update
+    # is amplified the same way.  Conservation: FP64 to rounding; the FP32
+    # state is rounded at every cell update, so the FP64 sums of the FP32
+    # states drift by ~1e-6 of sum |q| over the run.
+    t_long = 0.5
     for dtype, sym_tol, cons_tol in [("f64", 5e-5, 1e-12), ("f32", 5e-5, 1e-5)]:
-        _say(f"[gpu-fullsize] Orszag-Tang 1024^2 {dtype} to t = {t_long} (Courant 0.15)")
-        ctx = Context(s_long, dtype)
+        _say(f"[gpu-fullsize] Orszag-Tang 1024^2 {dtype} to t = {t_long} (Courant {s['cfl']})")
+        ctx = Context(s, dtype)
         U0 = ctx.prim_to_cons(torch.from_numpy(V).cuda())
         U, t, hist = advance(ctx, U0, t_end=t_long)
-        _, _, sums = ctx.step_info()
+        sums = ctx.get_sums()
         Ug = U.double().cpu().numpy()
         asym = _rot_asym(Ug)
         dcons = (np.abs(np.array(sums) - o_sums0)[[0, 1, 2, 4, 5, 6]] / scale[[0, 1, 2, 4, 5, 6]]).max()

@@ -3,9 +3,10 @@
 Bars: relative L1 per component (psi normalised by c_h sum|B|) after the
 full run, <= 1e-10 with FP64 state and <= 1e-5 with FP32 state, and
 element-wise, per component, max|q - q_ref| / max|q_ref| <= 1e-8 (FP64) and
-<= 1e-3 (FP32), so that a large error confined to a few cells cannot hide in
-the grid average; bitwise for uniform states and run-to-run repeats.  Shapes are ragged on purpose
-(several 64 x TY tiles plus partial tiles, z chunks with a partial tail).
+<= 2e-4 (FP32), so that a large error confined to a few cells cannot hide in
+the grid average; bitwise for uniform states and run-to-run repeats.
+Shapes are ragged on purpose (several 64 x TY tiles plus partial tiles, z
+chunks with a partial tail).
 """
 import sys
 
@@ -19,10 +20,11 @@ from tests.helpers import max_rel, rel_l1, rel_l1_own
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-10, "f32": 1e-5}
-# element-wise bar: a few hundred times the L1 bar (errors peak in a few
-# cells at discontinuities, where the limiter and the Riemann fan switch on
-# rounding-level differences); an O(1) error in one cell fails it
-TOL_MAX = {"f64": 1e-8, "f32": 1e-3}
+# element-wise bar: errors peak in a few cells at discontinuities, where the
+# limiter and the Riemann fan switch on rounding-level differences (measured
+# at most 4e-10 in FP64 and 2e-5 in FP32 over all cases); an O(1) error in
+# one cell fails it
+TOL_MAX = {"f64": 1e-8, "f32": 2e-4}
 
 
 def _say(msg):
@@ -112,6 +114,20 @@ def test_turbulence_mc_outflow(torch_cuda, dtype):
 def test_orszag_tang_ragged(torch_cuda, dtype):
     s, V = W.orszag_tang((100, 72))
     _compare(torch_cuda, "orszag_tang", s, V, dtype, nsteps=200)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_hlld_degenerate_switch_on(torch_cuda, dtype):
+    # no tangential field and Alfven speed above the sound speed on the left:
+    # every interface there is the degenerate case of the HLLD star states
+    # (fast = Alfven speed, D_a = 0), and near the switch-on front the
+    # tangential field is small, where the FP32 and FP64 decisions differ
+    # (the fastest cell sits on the switch-on front, where the FP32 state
+    # differs from the oracle's by up to ~1e-5 element-wise: the dt bar
+    # follows it)
+    s, V = W.switch_on_tube()
+    _compare(torch_cuda, "switch-on", s, V, dtype, t_end=s["t_end"],
+             dt_tol=1e-12 if dtype == "f64" else 1e-4)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

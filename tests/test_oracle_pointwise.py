@@ -312,14 +312,15 @@ def test_hlld_star_states_satisfy_jump_conditions():
     velocity S_M shared by both sides (the HLLD assumptions): momentum,
     tangential momentum, tangential field and energy fluxes of
     F*_a = F_a + S_a (U*_a - U_a) equal their physical form in the star
-    state.  The outer speeds are the Davis bounds of the pinned fast speed."""
+    state.  The outer speeds are min(u_L, u_R) - max(c_fL, c_fR) and
+    max(u_L, u_R) + max(c_fL, c_fR) of the pinned fast speed."""
     rng = np.random.default_rng(6)
     for qL, qR in _fan_cases(rng, 200):
         f = C.hlld_fan(qL, qR, GAMMA)
         sL, _, sM, _, sR = f["s"]
         cf = [C.fast_speed(np.r_[q[0], q[1:4], q[4], q[5:8], 0.0], GAMMA, 0) for q in (qL, qR)]
-        assert sL == min(qL[1] - cf[0], qR[1] - cf[1])
-        assert sR == max(qL[1] + cf[0], qR[1] + cf[1])
+        assert sL == min(qL[1], qR[1]) - max(cf)
+        assert sR == max(qL[1], qR[1]) + max(cf)
         bn = qL[5]
         pts = []
         for s_out, U, F, Us in [(sL, f["UL"], f["FL"], f["UsL"]), (sR, f["UR"], f["FR"], f["UsR"])]:
@@ -335,3 +336,51 @@ def test_hlld_star_states_satisfy_jump_conditions():
             vb = sM * bn + vt @ bt
             assert Fs[4] == pytest.approx((Us[4] + pt) * sM - bn * vb, abs=1e-13 * scale)
         assert pts[0] == pytest.approx(pts[1], abs=1e-13 * (1 + abs(pts[0])))
+
+
+def test_hlld_fan_stays_ordered_where_davis_bounds_meet_the_rotational_wave():
+    """With Davis's outer bounds S_R = max(u_L + c_fL, u_R + c_fR) (and the
+    S_M they give), D_R = rho_R (S_R - u_R)(S_R - S_M) - B_n^2 vanishes at
+    states that are not degenerate (tangential field present, S_M != u_R):
+    the rotational wave S*_R reaches S_R and the single-star tangential
+    velocity v_t - B_n B_t (S_M - u_R) / D_R diverges, its energy with it.
+    The oracle's HLLD outer speeds, min(u_L, u_R) - max(c_fL, c_fR) and
+    max(u_L, u_R) + max(c_fL, c_fR), keep that fan ordered with bounded star
+    states.  B_n is found by bisection where Davis's D_R changes sign."""
+    def cf(q):
+        return C.fast_speed(np.r_[q[0], q[1:4], q[4], q[5:8], 0.0], GAMMA, 0)
+
+    def davis_DR(bn):
+        qL = np.array([0.2, -0.8, 0.0, -0.2, 0.12, bn, 0.0, -0.05])
+        qR = np.array([0.15, -1.0, 0.0, -0.4, 0.07, bn, 0.0, -0.08])
+        sL = min(qL[1] - cf(qL), qR[1] - cf(qR))
+        sR = max(qL[1] + cf(qL), qR[1] + cf(qR))
+        ptL = qL[4] + 0.5 * qL[5:8] @ qL[5:8]
+        ptR = qR[4] + 0.5 * qR[5:8] @ qR[5:8]
+        mL, mR = (sL - qL[1]) * qL[0], (sR - qR[1]) * qR[0]
+        sM = (mR * qR[1] - mL * qL[1] - ptR + ptL) / (mR - mL)
+        return qR[0] * (sR - qR[1]) * (sR - sM) - bn * bn, sM, qL, qR
+
+    lo, hi = 0.3, 0.6
+    assert davis_DR(lo)[0] > 0 > davis_DR(hi)[0]
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if davis_DR(mid)[0] > 0 else (lo, mid)
+    DR, sM_davis, qL, qR = davis_DR(lo)
+    bn = qL[5]
+    assert abs(DR) <= 1e-14 * bn * bn
+    # not the degenerate case of the method: tangential field and S_M != u_R
+    assert abs(qR[7]) > 0.05 and abs(sM_davis - qR[1]) > 0.2
+    # Davis's single-star tangential velocity would be beyond any scale
+    assert abs(bn * qR[7] * (sM_davis - qR[1]) / DR) > 1e10
+    f = C.hlld_fan(qL, qR, GAMMA)
+    sL, ssL, sM, ssR, sR = f["s"]
+    assert sL < ssL < sM < ssR < sR
+    for s_out, q in ((sL, qL), (sR, qR)):
+        D = q[0] * (s_out - q[1]) * (s_out - sM) - bn * bn
+        assert D > 0.05 * (abs(q[0] * (s_out - q[1]) * (s_out - sM)) + bn * bn)
+    vmax = max(abs(qL[1:4]).max(), abs(qR[1:4]).max()) + max(cf(qL), cf(qR))
+    bmax = max(abs(qL[5:8]).max(), abs(qR[5:8]).max())
+    for U in (f["UsL"], f["UssL"], f["UssR"], f["UsR"]):
+        assert np.abs(U[1:4] / U[0]).max() <= vmax and np.abs(U[5:8]).max() <= 2 * bmax
+

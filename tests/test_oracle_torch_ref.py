@@ -95,7 +95,12 @@ def test_autograd_matches_finite_differences_of_c_oracle(name, setup, V):
         # scaled to the component's size so that the step is equally small
         # relative to every field (psi is ~30x smaller than the others)
         dirn[q] = _smooth(U0.shape[1:], 100 + q) * np.sqrt(np.mean(U0[q] ** 2))
-        eps = 1e-6
+        # the step is piecewise smooth (limiter branches, the min/max of the
+        # outer wave speeds): a central difference must not straddle a
+        # branch switch, and the generic turbulence state has a tie of the
+        # HLLD outer-speed maxima within 1e-6 of it along the density
+        # direction; 1e-7 keeps both sides on one branch (J rounding: 1e-9)
+        eps = 1e-7
         fd = (J_c(U0 + eps * dirn) - J_c(U0 - eps * dirn)) / (2 * eps)
         ad = float((g * dirn).sum())
         assert abs(fd - ad) <= 1e-6 * (abs(fd) + abs(ad)) + 1e-8, (q, fd, ad)
