@@ -71,13 +71,14 @@ mhd_status fail_hip(mhd_ctx *ctx, const char *what, hipError_t e)
         if (e_ != hipSuccess) return fail_hip((ctx), #call, e_); \
     } while (0)
 
-// Stage tile rows per workgroup (one wave per row).  FP32 PLM: 4 rows, three
+// Stage tile rows per workgroup (one wave per row; two with FP64 WENO-Z, see
+// stage_row_waves).  FP32 PLM: 4 rows, three
 // workgroups (12 waves) per compute unit at the 168-VGPR budget; measured
 // faster than 6 rows (two workgroups of 6 waves) by a third and than 8 rows
 // (one workgroup of 8 waves) by 13%.  FP32 WENO-Z: 8 rows, one workgroup of
 // 8 waves and 155 KB of LDS per compute unit; the three-cell y halo costs
 // half as much per cell as with 4 rows (measured 9% faster).  FP64 (register
-// bound at one wave per SIMD, WENO-Z at 140 KB of LDS): 4 rows.  1D: 1 row.
+// bound, WENO-Z at 140 KB of LDS): 4 rows.  1D: 1 row.
 template <typename T, int LIM, int NDIM> constexpr int tile_rows()
 {
     return NDIM == 1 ? 1 : (sizeof(T) == 4 && LIM == LIM_WENOZ ? 8 : 4);
@@ -136,6 +137,7 @@ mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, do
 {
     const bool rk3 = ctx->cfg.time_order == 3;
     constexpr int TY = tile_rows<T, LIM, NDIM>();
+    constexpr int NTH = TX * TY * stage_row_waves<T, LIM>();
     const Launch L = plan_stage(ctx, TY);
     if (L.nblocks > ctx->part_cap) return fail(ctx, MHD_ERR_ARG, "grid too large for partials buffer");
     if (ctx->no_alloc) {
@@ -173,27 +175,27 @@ mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, do
     a.uin = un;
     a.un = un;
     a.uout = u1;
-    hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 1, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+    hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 1, TY>), dim3(L.nblocks), dim3(NTH), 0,
                        ctx->stream, a);
     HIP_TRY(ctx, hipGetLastError());
     if (rk3) {
         T *u2 = (T *)ctx->u2_scratch;
         a.uin = u1;
         a.uout = u2;
-        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 3, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 3, TY>), dim3(L.nblocks), dim3(NTH), 0,
                            ctx->stream, a);
         HIP_TRY(ctx, hipGetLastError());
         if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
         a.uin = u2;
         a.uout = unext;
-        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 4, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 4, TY>), dim3(L.nblocks), dim3(NTH), 0,
                            ctx->stream, a);
         HIP_TRY(ctx, hipGetLastError());
     } else {
         if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
         a.uin = u1;
         a.uout = unext;
-        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 2, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 2, TY>), dim3(L.nblocks), dim3(NTH), 0,
                            ctx->stream, a);
         HIP_TRY(ctx, hipGetLastError());
     }
@@ -213,6 +215,7 @@ template <typename T, int SOLVER, int LIM>
 mhd_status launch_step_ct(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, double ch, double damp)
 {
     constexpr int TY = tile_rows<T, LIM, 3>();
+    constexpr int NTH = TX * TY * stage_row_waves<T, LIM>();
     const bool rk3 = ctx->cfg.time_order == 3;
     const Launch L = plan_stage(ctx, TY);
     StageArgs<T> a;
@@ -266,7 +269,7 @@ mhd_status launch_step_ct(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt,
         a.uin = uin;
         a.un = un;
         a.uout = uout;
-        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, 3, KIND, TY, true>), dim3(L.nblocks), dim3(TX * TY), 0,
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, 3, KIND, TY, true>), dim3(L.nblocks), dim3(NTH), 0,
                            ctx->stream, a);
         HIP_TRY(ctx, hipGetLastError());
         c.uin = uin;
@@ -364,6 +367,7 @@ mhd_status launch_adjoint(mhd_ctx *ctx, const T *un, const T *u1, const double *
     if (!u1) {
         // recompute the stage-1 state into scratch with the forward kernel
         constexpr int TY = tile_rows<T, LIM, NDIM>();
+        constexpr int NTH = TX * TY * stage_row_waves<T, LIM>();
         const Launch L = plan_stage(ctx, TY);
         StageArgs<T> a;
         a.part = ctx->part;
@@ -390,7 +394,7 @@ mhd_status launch_adjoint(mhd_ctx *ctx, const T *un, const T *u1, const double *
         a.uin = un;
         a.un = un;
         a.uout = (T *)ctx->u1_scratch;
-        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 1, TY>), dim3(L.nblocks), dim3(TX * TY), 0,
+        hipLaunchKernelGGL((stage_kernel<T, SOLVER, LIM, NDIM, 1, TY>), dim3(L.nblocks), dim3(NTH), 0,
                            ctx->stream, a);
         HIP_TRY(ctx, hipGetLastError());
         u1 = (const T *)ctx->u1_scratch;

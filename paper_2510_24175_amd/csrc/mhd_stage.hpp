@@ -157,12 +157,25 @@ __device__ __forceinline__ double wave_max(double v)
 // unit; the last stage 165, three).  FP32 WENO-Z: 2 (256 registers; its
 // 8-row workgroups take 155 KB of LDS, one per compute unit).  FP64 PLM: 2
 // (256 registers; the HLLD kernels spill some of them, and still run 11%
-// faster than at one wave per SIMD without spills).  FP64 WENO-Z: 1 (140 KB
-// of LDS, the fluxes laid over the primitive plane, allows one 4-wave
-// workgroup per compute unit).
+// faster than at one wave per SIMD without spills).  FP64 WENO-Z: 2 (140 KB
+// of LDS, the fluxes laid over the primitive plane, allows one workgroup per
+// compute unit: 4 rows with two waves each, the helper waves below; 256
+// registers, some spilled: the 416^3 SSP-RK3 step runs in 50.5 ms against
+// 58.8 ms with one 4-wave workgroup at 512 registers).
 template <typename T, int LIM> constexpr int stage_min_waves()
 {
-    return sizeof(T) == 4 ? (LIM == LIM_WENOZ ? 2 : 3) : (LIM == LIM_WENOZ ? 1 : 2);
+    return sizeof(T) == 4 ? (LIM == LIM_WENOZ ? 2 : 3) : 2;
+}
+
+// Waves per tile row.  FP64 WENO-Z's arrays leave room for one workgroup per
+// compute unit; a second wave per row (a helper that owns no column) shares
+// the halo conversions, the WENO-Z reconstructions and the x/y face fluxes
+// of the plane, so that those phases run two waves per SIMD instead of one.
+// The z march (register window, z faces) and the update stay with the
+// column owners.
+template <typename T, int LIM> constexpr int stage_row_waves()
+{
+    return (sizeof(T) == 8 && LIM == LIM_WENOZ) ? 2 : 1;
 }
 
 // Stage kinds of the Runge-Kutta integrators (KIND): 1 U1 = Un + dt L(Un)
@@ -173,7 +186,8 @@ template <typename T, int LIM> constexpr int stage_min_waves()
 constexpr bool last_stage(int kind) { return kind == 2 || kind == 4; }
 
 template <typename T, int SOLVER, int LIM, int NDIM, int KIND, int TY, bool CT = false>
-__global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_kernel(const StageArgs<T> a)
+__global__ void __launch_bounds__(TX *TY *(stage_row_waves<T, LIM>()), (stage_min_waves<T, LIM>()))
+stage_kernel(const StageArgs<T> a)
 {
     constexpr bool WENO = LIM == LIM_WENOZ;
     // with constrained transport the cell field is final only after the
@@ -181,7 +195,8 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
     constexpr bool LAST = last_stage(KIND) && !CT;
     static_assert(!CT || NDIM == 3, "constrained transport is three-dimensional");
     constexpr int H = WENO ? 3 : 2;        // stencil half width (ghost layers)
-    constexpr int NT = TX * TY;
+    constexpr int NW = TY * stage_row_waves<T, LIM>();  // waves: TY column owners, then helpers
+    constexpr int NT = TX * NW;
     constexpr int HY = NDIM >= 2 ? H : 0;  // y halo width in LDS
     constexpr int PX = TX + 2 * H;         // LDS row pitch
     constexpr int PY = TY + 2 * HY;        // LDS rows
@@ -225,8 +240,9 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
 
     const int t = threadIdx.x;
     const int tx = t & (TX - 1);
-    const int ty = t / TX;
+    const int ty = t / TX;  // tile row of a column owner (>= TY: helper)
     const int wave = __builtin_amdgcn_readfirstlane(ty);
+    const bool owner = wave < TY;  // wave-uniform
     const int lb = logical_block(blockIdx.x, a.nblocks);
     const int tile_x = lb % a.tiles_x;
     const int rest = lb / a.tiles_x;
@@ -236,7 +252,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
     const int k0 = chunk * a.kz;
     const int k1 = min(k0 + a.kz, a.nz);
     const int i = i0 + tx, j = j0 + ty;
-    const bool active = (i < a.nx) & (j < a.ny);
+    const bool active = owner & (i < a.nx) & (j < a.ny);
 
     // own column (remapped so that columns just past the grid edge hold the
     // ghost values their active neighbours need)
@@ -336,7 +352,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
     constexpr int ZW = WENO ? 4 : 2;
     constexpr int ZC = WENO ? 1 : 0;       // window slot of plane k
     T Wz[ZW][NQ], D0[NQ], ZT[NQ], Fzm[NQ];
-    if (NDIM == 3) {
+    if (NDIM == 3 && owner) {
         T VL[NQ], VR[NQ];
         if constexpr (WENO) {
             // cell k0-1 gives the lower state of face k0-1/2, cell k0 the
@@ -370,7 +386,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             face_flux<T, SOLVER, true>(VL, VR, 2, a.ph, Fzm, a.uin[11 * a.ncell + zoff(k0) + own]);
         else
             face_flux<T, SOLVER>(VL, VR, 2, a.ph, Fzm);
-    } else {
+    } else if (owner) {
         prim_at(own, Wz[ZC]);
     }
 
@@ -385,10 +401,11 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
 
     // The stage combine's inputs at the thread's own cell are loaded at the
     // top of the plane, so that their latency hides behind the face phases,
-    // where registers allow: FP32 PLM (measured 2% faster) and FP64 WENO-Z
-    // (11%); FP64 PLM would spill and FP32 WENO-Z runs at two waves per SIMD
-    // (25% and 3% slower), and those load them at the update.
-    constexpr bool PREFETCH = (sizeof(T) == 4) != WENO;
+    // where registers allow: FP32 PLM (measured 2% faster).  FP64 PLM would
+    // spill (25% slower), FP32 WENO-Z runs at two waves per SIMD (3% slower),
+    // and FP64 WENO-Z with its helper waves spills 2.2x more (416^3 step 50.5
+    // against 78.5 ms); those load them at the update.
+    constexpr bool PREFETCH = (sizeof(T) == 4) && !WENO;
     auto load_combine = [&](long long c, T *cin, T *cun) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -404,8 +421,10 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
         // the fluxes of the previous plane sit where P goes
         if (ALIAS && k > k0) __syncthreads();
         // (a) primitives of plane k into LDS: own column and halo cell
+        if (owner) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) P[q * PLANE + own_slot] = Wz[ZC][q];
+            for (int q = 0; q < NQ; ++q) P[q * PLANE + own_slot] = Wz[ZC][q];
+        }
 #pragma unroll
         for (int m = 0; m < HPT; ++m) {
             if (t + m * NT < NH) {
@@ -417,7 +436,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
         }
         // (b) z-face k+1/2 from the register window
         T Fzp[NQ], D1[NQ];
-        if (NDIM == 3) {
+        if (NDIM == 3 && owner) {
             T Vn[NQ], VL[NQ], VR[NQ];
             prim_at(zoff(k + ZW - ZC) + own, Vn);  // PLM: V(k+2); WENO-Z: V(k+3)
             if constexpr (WENO) {
@@ -455,7 +474,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             // each from the five cells centred on it: x items for cells
             // -1 .. TX of each row, y items for rows -1 .. TY of each column.
             // Direction only changes addresses, so chunks mix the two.
-            for (int ch = wave; ch < NRCH; ch += TY) {
+            for (int ch = wave; ch < NRCH; ch += NW) {
                 const int it = ch * TX + tx;
                 if (it < NRX + NRY) {
                     const T *src;
@@ -491,7 +510,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             // (c1) face fluxes from the edge values: x face f of row r between
             // cells f-1 and f, y face r of column c between rows r-1 and r;
             // (the fluxes overwrite P when the LDS is aliased)
-            for (int ch = wave; ch < NCHUNK; ch += TY) {
+            for (int ch = wave; ch < NCHUNK; ch += NW) {
                 T VL[NQ], VR[NQ];
                 if (ch < NCHX) {
                     const int it = ch * TX + tx;
@@ -525,7 +544,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
             // one chunk per wave at a time; x items are padded to whole chunks so
             // every chunk is a single direction and the solver is inlined with a
             // compile-time frame.
-            for (int ch = wave; ch < NCHUNK; ch += TY) {
+            for (int ch = wave; ch < NCHUNK; ch += NW) {
                 if (ch < NCHX) {
                     const int it = ch * TX + tx;
                     const bool valid = it < NFX;
@@ -602,7 +621,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
                 }
             }
         }
-        if (NDIM == 3) {
+        if (NDIM == 3 && owner) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 Fzm[q] = Fzp[q];
@@ -636,7 +655,7 @@ __global__ void __launch_bounds__(TX *TY, (stage_min_waves<T, LIM>())) stage_ker
         vals[1] = wave_max(cmax);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) vals[2 + q] = wave_sum(sum[q]);
-        if (tx == 0) {
+        if (tx == 0 && owner) {
 #pragma unroll
             for (int e = 0; e < NPART; ++e) red[ty * NPART + e] = vals[e];
         }
