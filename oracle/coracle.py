@@ -65,6 +65,7 @@ def lib():
             "orc_step": [cp, dp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
             "orc_sums": [cp, dp, dp],
             "orc_face_flux": [cp, ctypes.c_int, dp, dp, ctypes.c_double, dp],
+            "orc_ct_emf": [cp, dp, dp],
         }.items():
             f = getattr(L, name)
             f.argtypes = args
@@ -109,6 +110,14 @@ def _check(st, what):
         raise OracleError(f"{what}: bad argument (status {st})")
 
 
+def _ct_mode(setup):
+    """0 without constrained transport, 1 with the arithmetic-mean edge EMF,
+    2 with the upwind edge EMF (setup "ct_emf": "mean" or "upwind")."""
+    if not setup.get("ct", False):
+        return 0
+    return {"mean": 1, "upwind": 2}[setup.get("ct_emf", "mean")]
+
+
 class Oracle:
     """FP64 CPU reference for one problem setup (a dict, see the workloads)."""
 
@@ -129,7 +138,7 @@ class Oracle:
         c.cfl = float(setup["cfl"])
         c.glm_alpha = float(setup.get("glm_alpha", 0.1))
         c.time_order = int(setup.get("time_order", 2))
-        c.ct = 1 if setup.get("ct", False) else 0
+        c.ct = _ct_mode(setup)
         self.cfg = c
         self.nstate = 12 if c.ct else 9
         self.shape = (self.nstate, int(setup["n"][2]), int(setup["n"][1]), int(setup["n"][0]))
@@ -186,6 +195,14 @@ class Oracle:
         out = np.zeros(9)
         _check(lib().orc_sums(ctypes.byref(self.cfg), _p(U), _p(out)), "sums")
         return out
+
+    def ct_emf(self, U):
+        """Edge EMFs (3, nz, ny, nx) of a constrained-transport state: Ex,
+        Ey, Ez on each cell's lower edges."""
+        U = _f64(U).reshape(self.shape)
+        E = np.zeros((3,) + self.shape[1:])
+        _check(lib().orc_ct_emf(ctypes.byref(self.cfg), _p(U), _p(E)), "ct_emf")
+        return E
 
     def div_b(self, U):
         """Divergence of the face field of each cell (constrained transport):

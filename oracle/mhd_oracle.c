@@ -45,12 +45,15 @@
  *   CT       : (the paper's weak-scaling runs) constrained transport (Evans &
  *              Hawley 1988) in 3D on periodic grids, GLM off: the field lives
  *              on the cell faces, the normal field of each Riemann problem is
- *              the face value, edge EMFs are the arithmetic mean of the four
- *              face fluxes around the edge (Balsara & Spicer 1999; the paper
- *              also cites the upwind CT of Londrillo & Del Zanna 2004, whose
- *              EMF it does not print), faces advance by the discrete curl of
- *              the EMFs with the same Runge-Kutta stages, and the cell field
- *              is the mean of each cell's two faces per axis.
+ *              the face value, faces advance by the discrete curl of the edge
+ *              EMFs with the same Runge-Kutta stages, and the cell field is
+ *              the mean of each cell's two faces per axis.  Edge EMFs (ct = 1)
+ *              the arithmetic mean of the four face fluxes around the edge
+ *              (Balsara & Spicer 1999), or (ct = 2) the upwind EMF of the
+ *              upwind constrained transport of Londrillo & Del Zanna (2004),
+ *              which the paper cites: the two-dimensional HLL average of the
+ *              EMFs of the four states meeting at the edge, plus an HLL
+ *              dissipation term per transverse direction.
  *
  * External arrays are structure-of-arrays, shape [9][nz][ny][nx] ([12] with
  * constrained transport: the face field on each cell's lower x, y, z face
@@ -647,23 +650,19 @@ static void rhs_from_prims(const orc_cfg *cfg, const grid *G, const double *W, d
     }
 }
 
-/* Constrained transport (Evans & Hawley 1988), edge EMFs as the arithmetic
- * mean of the four face fluxes around each edge (Balsara & Spicer 1999),
- * E = -v x B so that F_x(By) = -Ez, F_y(Bx) = Ez, F_y(Bz) = -Ex, F_z(By) = Ex,
- * F_z(Bx) = -Ey, F_x(Bz) = Ey.  E[3][nc] holds the EMFs on each cell's lower
- * edges: Ex at (j-1/2, k-1/2), Ey at (i-1/2, k-1/2), Ez at (i-1/2, j-1/2).
- * The face rates dB/dt = -curl E are written to L[FBX..FBZ]. */
-static void ct_face_rates(const orc_cfg *cfg, const double *Fl, double *L)
+/* Constrained transport (Evans & Hawley 1988).  E = -v x B, so that
+ * F_x(By) = -Ez, F_y(Bx) = Ez, F_y(Bz) = -Ex, F_z(By) = Ex, F_z(Bx) = -Ey,
+ * F_x(Bz) = Ey.  E[3][nc] holds the EMFs on each cell's lower edges: Ex at
+ * (j-1/2, k-1/2), Ey at (i-1/2, k-1/2), Ez at (i-1/2, j-1/2). */
+#define CI(i, j, k) ((((k) + nz) % nz * ny + ((j) + ny) % ny) * nx + ((i) + nx) % nx)
+
+/* Edge EMFs as the arithmetic mean of the four face fluxes around each edge
+ * (Balsara & Spicer 1999). */
+static void ct_emf_mean(const orc_cfg *cfg, const double *Fl, double *E)
 {
     int64_t nx = cfg->n[0], ny = cfg->n[1], nz = cfg->n[2], nc = nx * ny * nz;
-    double dx = (cfg->hi[0] - cfg->lo[0]) / (double)nx;
-    double dy = (cfg->hi[1] - cfg->lo[1]) / (double)ny;
-    double dz = (cfg->hi[2] - cfg->lo[2]) / (double)nz;
     const double *FxBy = Fl, *FxBz = Fl + nc, *FyBx = Fl + 2 * nc, *FyBz = Fl + 3 * nc;
     const double *FzBx = Fl + 4 * nc, *FzBy = Fl + 5 * nc;
-    double *E = (double *)malloc(sizeof(double) * 3 * nc);
-    if (!E) return;
-#define CI(i, j, k) ((((k) + nz) % nz * ny + ((j) + ny) % ny) * nx + ((i) + nx) % nx)
 #pragma omp parallel for collapse(2) schedule(static)
     for (int64_t k = 0; k < nz; ++k)
         for (int64_t j = 0; j < ny; ++j)
@@ -673,6 +672,104 @@ static void ct_face_rates(const orc_cfg *cfg, const double *Fl, double *L)
                 E[nc + c] = 0.25 * (FxBz[CI(i, j, k - 1)] + FxBz[c] - FzBx[CI(i - 1, j, k)] - FzBx[c]);
                 E[2 * nc + c] = 0.25 * (-FxBy[CI(i, j - 1, k)] - FxBy[c] + FyBx[CI(i - 1, j, k)] + FyBx[c]);
             }
+}
+
+/* Upwind edge EMFs (Londrillo & Del Zanna 2004, upwind constrained
+ * transport with HLL averaging).  For the EMF along axis e at an edge, with
+ * (e, p, q) cyclic, four cells meet at the edge: the lower or upper one along
+ * p (a = 0, 1) and along q (b = 0, 1).  Each gives a state at the edge:
+ *   v^ab  = cell velocity + (1/2 - a) s_p(v) + (1/2 - b) s_q(v),
+ *   B_q^a = the q-face field on side a, + (1/2 - a) s_p(B_q) along p,
+ *   B_p^b = the p-face field on side b, + (1/2 - b) s_q(B_p) along q,
+ *   E^ab  = -(v_p^ab B_q^a - v_q^ab B_p^b),
+ * with s the minmod-limited slopes of cell (or face) values along an axis.
+ * With HLL speed bounds a_p+ = max(0, v_p + c_f,p), a_p- = max(0, c_f,p - v_p)
+ * over the four cells (and the same along q),
+ *   E = sum_ab w_p^a w_q^b E^ab + a_p+ a_p- (B_q^1 - B_q^0) / (a_p+ + a_p-)
+ *                                - a_q+ a_q- (B_p^1 - B_p^0) / (a_q+ + a_q-),
+ * w_p^0 = a_p+ / (a_p+ + a_p-), w_p^1 = a_p- / (a_p+ + a_p-): along p the
+ * HLL flux of B_q (F_p(B_q) = -E_e), along q that of B_p (F_q(B_p) = E_e).
+ * Where the fields vary along p alone it is the one-dimensional HLL flux of
+ * B_q at the p face.  W: primitives with ghosts (cell-centred B the face
+ * means); U: the state with the face field. */
+static void ct_emf_upwind(const orc_cfg *cfg, const grid *G, const double *W, const double *U,
+                          double *E)
+{
+    int64_t nx = cfg->n[0], ny = cfg->n[1], nz = cfg->n[2], nc = nx * ny * nz;
+    const double gamma = cfg->gamma;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t c = CI(i, j, k);
+                for (int e = 0; e < 3; ++e) {
+                    const int p = (e + 1) % 3, q = (e + 2) % 3;
+                    int64_t dp[3] = {0, 0, 0}, dq[3] = {0, 0, 0};
+                    dp[p] = 1;
+                    dq[q] = 1;
+                    double vp[2][2], vq[2][2];
+                    double app = 0.0, apm = 0.0, aqp = 0.0, aqm = 0.0;
+                    for (int a = 0; a < 2; ++a)
+                        for (int b = 0; b < 2; ++b) {
+                            /* cell (a, b) around the edge */
+                            int64_t x = i + (a - 1) * dp[0] + (b - 1) * dq[0];
+                            int64_t y = j + (a - 1) * dp[1] + (b - 1) * dq[1];
+                            int64_t z = k + (a - 1) * dp[2] + (b - 1) * dq[2];
+                            const double *V0 = &W[NV * pidx(G, x, y, z)];
+                            const double *Vpm = &W[NV * pidx(G, x - dp[0], y - dp[1], z - dp[2])];
+                            const double *Vpp = &W[NV * pidx(G, x + dp[0], y + dp[1], z + dp[2])];
+                            const double *Vqm = &W[NV * pidx(G, x - dq[0], y - dq[1], z - dq[2])];
+                            const double *Vqp = &W[NV * pidx(G, x + dq[0], y + dq[1], z + dq[2])];
+                            const int up = VX + p, uq = VX + q;
+                            double spp = limited_slope(ORC_MINMOD, V0[up] - Vpm[up], Vpp[up] - V0[up]);
+                            double sqp = limited_slope(ORC_MINMOD, V0[up] - Vqm[up], Vqp[up] - V0[up]);
+                            double spq = limited_slope(ORC_MINMOD, V0[uq] - Vpm[uq], Vpp[uq] - V0[uq]);
+                            double sqq = limited_slope(ORC_MINMOD, V0[uq] - Vqm[uq], Vqp[uq] - V0[uq]);
+                            vp[a][b] = V0[up] + (0.5 - a) * spp + (0.5 - b) * sqp;
+                            vq[a][b] = V0[uq] + (0.5 - a) * spq + (0.5 - b) * sqq;
+                            double cp = fast_speed(V0, gamma, p), cq = fast_speed(V0, gamma, q);
+                            app = fmax(app, V0[up] + cp);
+                            apm = fmax(apm, cp - V0[up]);
+                            aqp = fmax(aqp, V0[uq] + cq);
+                            aqm = fmax(aqm, cq - V0[uq]);
+                        }
+                    double Bq[2], Bp[2];
+                    for (int a = 0; a < 2; ++a) {
+                        /* q face of the cell on side a along p (at the edge's q) */
+                        int64_t x = i + (a - 1) * dp[0], y = j + (a - 1) * dp[1], z = k + (a - 1) * dp[2];
+                        const double *F = &U[(FBX + q) * nc];
+                        double f0 = F[CI(x, y, z)];
+                        double s = limited_slope(ORC_MINMOD, f0 - F[CI(x - dp[0], y - dp[1], z - dp[2])],
+                                                 F[CI(x + dp[0], y + dp[1], z + dp[2])] - f0);
+                        Bq[a] = f0 + (0.5 - a) * s;
+                    }
+                    for (int b = 0; b < 2; ++b) {
+                        int64_t x = i + (b - 1) * dq[0], y = j + (b - 1) * dq[1], z = k + (b - 1) * dq[2];
+                        const double *F = &U[(FBX + p) * nc];
+                        double f0 = F[CI(x, y, z)];
+                        double s = limited_slope(ORC_MINMOD, f0 - F[CI(x - dq[0], y - dq[1], z - dq[2])],
+                                                 F[CI(x + dq[0], y + dq[1], z + dq[2])] - f0);
+                        Bp[b] = f0 + (0.5 - b) * s;
+                    }
+                    double sp = app + apm, sq = aqp + aqm;
+                    double wp[2] = {app / sp, apm / sp}, wq[2] = {aqp / sq, aqm / sq};
+                    double Em = 0.0;
+                    for (int a = 0; a < 2; ++a)
+                        for (int b = 0; b < 2; ++b)
+                            Em += wp[a] * wq[b] * (-(vp[a][b] * Bq[a] - vq[a][b] * Bp[b]));
+                    Em += app * apm / sp * (Bq[1] - Bq[0]) - aqp * aqm / sq * (Bp[1] - Bp[0]);
+                    E[e * nc + c] = Em;
+                }
+            }
+}
+
+/* Face rates dB/dt = -curl E of every cell's lower faces, to L[FBX..FBZ]. */
+static void ct_face_rates(const orc_cfg *cfg, const double *E, double *L)
+{
+    int64_t nx = cfg->n[0], ny = cfg->n[1], nz = cfg->n[2], nc = nx * ny * nz;
+    double dx = (cfg->hi[0] - cfg->lo[0]) / (double)nx;
+    double dy = (cfg->hi[1] - cfg->lo[1]) / (double)ny;
+    double dz = (cfg->hi[2] - cfg->lo[2]) / (double)nz;
     const double *Ex = E, *Ey = E + nc, *Ez = E + 2 * nc;
 #pragma omp parallel for collapse(2) schedule(static)
     for (int64_t k = 0; k < nz; ++k)
@@ -683,7 +780,6 @@ static void ct_face_rates(const orc_cfg *cfg, const double *Fl, double *L)
                 L[FBY * nc + c] = -((Ex[CI(i, j, k + 1)] - Ex[c]) / dz - (Ez[CI(i + 1, j, k)] - Ez[c]) / dx);
                 L[FBZ * nc + c] = -((Ey[CI(i + 1, j, k)] - Ey[c]) / dx - (Ex[CI(i, j + 1, k)] - Ex[c]) / dy);
             }
-    free(E);
 }
 
 /* cell-centred B of every cell from its two faces along each axis */
@@ -702,6 +798,17 @@ static void ct_cell_field(const orc_cfg *cfg, double *U)
 #undef CI
 }
 
+/* Edge EMFs E[3][nc] of the state (constrained transport), from the face
+ * fluxes Fl (ct = 1) or the primitives W with ghosts (ct = 2). */
+static void ct_emf(const orc_cfg *cfg, const grid *G, const double *W, const double *U,
+                   const double *Fl, double *E)
+{
+    if (cfg->ct == 2)
+        ct_emf_upwind(cfg, G, W, U, E);
+    else
+        ct_emf_mean(cfg, Fl, E);
+}
+
 static int rhs(const orc_cfg *cfg, const double *U, double ch, double *L)
 {
     grid G;
@@ -709,16 +816,22 @@ static int rhs(const orc_cfg *cfg, const double *U, double ch, double *L)
     int64_t nc = cfg->n[0] * cfg->n[1] * cfg->n[2];
     double *W = (double *)malloc(sizeof(double) * NV * G.cells);
     double *Fl = cfg->ct ? (double *)malloc(sizeof(double) * 6 * nc) : NULL;
-    if (!W || (cfg->ct && !Fl)) {
+    double *E = cfg->ct ? (double *)malloc(sizeof(double) * 3 * nc) : NULL;
+    if (!W || (cfg->ct && (!Fl || !E))) {
         free(W);
         free(Fl);
+        free(E);
         return 2;
     }
     int ok = load_prims(cfg, &G, U, W);
     if (ok) rhs_from_prims(cfg, &G, W, ch, L, cfg->ct ? U : NULL, Fl);
-    if (ok && cfg->ct) ct_face_rates(cfg, Fl, L);
+    if (ok && cfg->ct) {
+        ct_emf(cfg, &G, W, U, Fl, E);
+        ct_face_rates(cfg, E, L);
+    }
     free(W);
     free(Fl);
+    free(E);
     return ok ? 0 : 1;
 }
 
@@ -736,7 +849,7 @@ static int cfg_ok(const orc_cfg *cfg)
     }
     if (cfg->limiter < ORC_MINMOD || cfg->limiter > ORC_WENOZ) return 0;
     if (cfg->time_order != 2 && cfg->time_order != 3) return 0;
-    if (cfg->ct != 0 && cfg->ct != 1) return 0;
+    if (cfg->ct < 0 || cfg->ct > 2) return 0;
     if (cfg->ct) {
         /* three-dimensional, periodic, no GLM */
         if (cfg->ndim != 3 || cfg->glm) return 0;
@@ -939,6 +1052,34 @@ void orc_rotated_flux(int riemann, const double *qL, const double *qR, double ga
         hlld_flux(qL, qR, gamma, F);
     else
         hll_flux(qL, qR, gamma, F);
+}
+
+/* edge EMFs E[3][nc] of a constrained-transport state (for the pin tests):
+ * Ex, Ey, Ez on each cell's lower edges; c_h is unused without GLM */
+int orc_ct_emf(const orc_cfg *cfg, const double *U, double *E)
+{
+    if (!cfg_ok(cfg) || !cfg->ct) return 2;
+    grid G;
+    grid_make(cfg, &G);
+    int64_t nc = ncells(cfg);
+    double *W = (double *)malloc(sizeof(double) * NV * G.cells);
+    double *Fl = (double *)malloc(sizeof(double) * 6 * nc);
+    double *L = (double *)malloc(sizeof(double) * NV * nc);
+    if (!W || !Fl || !L) {
+        free(W);
+        free(Fl);
+        free(L);
+        return 2;
+    }
+    int ok = load_prims(cfg, &G, U, W);
+    if (ok) {
+        rhs_from_prims(cfg, &G, W, 1.0, L, U, Fl);
+        ct_emf(cfg, &G, W, U, Fl, E);
+    }
+    free(W);
+    free(Fl);
+    free(L);
+    return ok ? 0 : 1;
 }
 
 /* host threads of the parallel loops (for the timed CPU baseline): set and

@@ -376,14 +376,15 @@ def _with_faces(V, faces):
 
 
 def orszag_tang_3d_ct(n, eps=0.2, riemann="hlld", cfl=0.3, limiter="wenoz", time_order=3,
-                      t_end=None):
+                      t_end=None, emf="mean"):
     """The 3D Orszag-Tang vortex of ``orszag_tang_3d`` for constrained
     transport (GLM off): face fields bx = -B0 sin 2pi y, by = B0 sin 4pi x,
     bz = 0 sampled on the faces (each independent of its own coordinate, so
-    the discrete divergence is exactly zero)."""
+    the discrete divergence is exactly zero).  emf: "mean" (arithmetic mean
+    of the face fluxes) or "upwind" edge EMFs."""
     s, V = orszag_tang_3d(n, eps=eps, riemann=riemann, cfl=cfl, limiter=limiter,
                           time_order=time_order, t_end=t_end)
-    s["name"], s["ct"], s["glm"] = "orszag_tang_3d_ct", True, False
+    s["name"], s["ct"], s["glm"], s["ct_emf"] = "orszag_tang_3d_ct", True, False, emf
     (xc, _, _), (yc, _, _), _ = _face_coords(s)
     b0 = 1.0 / math.sqrt(4 * math.pi)
     nx, ny, nz = s["n"]
@@ -393,15 +394,16 @@ def orszag_tang_3d_ct(n, eps=0.2, riemann="hlld", cfl=0.3, limiter="wenoz", time
     return s, _with_faces(V, faces)
 
 
-def cpa_wave_3d_ct(n, amplitude=0.1, riemann="hlld", cfl=0.3, limiter="wenoz", time_order=3):
+def cpa_wave_3d_ct(n, amplitude=0.1, riemann="hlld", cfl=0.3, limiter="wenoz", time_order=3,
+                   emf="mean"):
     """The diagonal circularly polarised Alfven wave of ``cpa_wave_3d`` for
     constrained transport: the face field is b0 khat plus the discrete curl
     of the edge-centred potential A = a/(2 pi |k|) (sin phi e1 + cos phi e2),
     whose continuous curl is the wave's perturbation a (sin phi e1 +
-    cos phi e2)."""
+    cos phi e2).  emf as for ``orszag_tang_3d_ct``."""
     s, V = cpa_wave_3d(n, amplitude=amplitude, riemann=riemann, cfl=cfl, limiter=limiter,
                        time_order=time_order)
-    s["name"], s["ct"], s["glm"] = "cpa3d_ct", True, False
+    s["name"], s["ct"], s["glm"], s["ct_emf"] = "cpa3d_ct", True, False, emf
     k = np.array([1.0, 1.0, 1.0])
     kn = np.linalg.norm(k)
     kh = k / kn

@@ -1,7 +1,8 @@
 """Pins of the oracle's constrained transport (the divergence control of
 the paper's weak-scaling runs, section "Results for gPLUTO"; Evans & Hawley
-1988), edge EMFs as the arithmetic mean of the four face fluxes around
-each edge (Balsara & Spicer 1999).
+1988), with edge EMFs either the arithmetic mean of the four face fluxes
+around each edge (Balsara & Spicer 1999) or the upwind EMF of Londrillo &
+Del Zanna (2004) (two-dimensional HLL average of the four edge states).
 
 * the discrete divergence of the face field stays at rounding, for initial
   fields whose face divergence is zero (a face component independent of its
@@ -13,7 +14,10 @@ each edge (Balsara & Spicer 1999).
   (face components move with their faces);
 * the diagonal circularly polarised Alfven wave converges at second order
   (the staggered update is second order) - a wrong sign or edge in any EMF
-  term breaks it, since the diagonal wave drives all three.
+  term breaks it, since the diagonal wave drives all three;
+* the upwind EMF reduces, where the fields vary along one axis only, to the
+  one-dimensional HLL flux of the transverse field at that axis' face
+  (minmod-reconstructed face states, speed bounds from the two cells).
 """
 import math
 
@@ -30,13 +34,17 @@ def _scheme(s, limiter, time_order):
     return s
 
 
+EMFS = ["mean", "upwind"]
+
+
+@pytest.mark.parametrize("emf", EMFS)
 @pytest.mark.parametrize("limiter,time_order", [("wenoz", 3), ("minmod", 2)])
 @pytest.mark.parametrize("gen", ["ot", "cpa"])
-def test_face_divergence_stays_at_rounding(gen, limiter, time_order):
+def test_face_divergence_stays_at_rounding(gen, limiter, time_order, emf):
     if gen == "ot":
-        s, V = W.orszag_tang_3d_ct((16, 12, 10))
+        s, V = W.orszag_tang_3d_ct((16, 12, 10), emf=emf)
     else:
-        s, V = W.cpa_wave_3d_ct((12, 12, 12))
+        s, V = W.cpa_wave_3d_ct((12, 12, 12), emf=emf)
     s = _scheme(s, limiter, time_order)
     o = C.Oracle(s)
     U0 = o.prim_to_cons(V)
@@ -49,8 +57,9 @@ def test_face_divergence_stays_at_rounding(gen, limiter, time_order):
     np.testing.assert_allclose(U[7], 0.5 * (U[11] + np.roll(U[11], -1, axis=0)), rtol=0, atol=1e-15)
 
 
-def test_periodic_conservation():
-    s, V = W.orszag_tang_3d_ct((16, 12, 10))
+@pytest.mark.parametrize("emf", EMFS)
+def test_periodic_conservation(emf):
+    s, V = W.orszag_tang_3d_ct((16, 12, 10), emf=emf)
     o = C.Oracle(s)
     U0 = o.prim_to_cons(V)
     U, _, _ = o.run(U0, nsteps=25)
@@ -64,10 +73,11 @@ def test_periodic_conservation():
         assert abs(U[9 + d].mean() - U0[9 + d].mean()) <= 1e-15
 
 
+@pytest.mark.parametrize("emf", EMFS)
 @pytest.mark.parametrize("time_order", [2, 3])
-def test_uniform_state_is_a_fixed_point(time_order):
+def test_uniform_state_is_a_fixed_point(time_order, emf):
     s, V = W.uniform((6, 5, 4), ndim=3)
-    s.update(ct=True, glm=False, limiter="wenoz", time_order=time_order)
+    s.update(ct=True, glm=False, limiter="wenoz", time_order=time_order, ct_emf=emf)
     W12 = np.zeros((12,) + V.shape[1:])
     W12[:9] = V
     W12[8] = 0.0
@@ -81,8 +91,9 @@ def test_uniform_state_is_a_fixed_point(time_order):
         np.testing.assert_allclose(U, U0, rtol=1e-14, atol=0)
 
 
-def test_orszag_tang_half_turn_symmetry():
-    s, V = W.orszag_tang_3d_ct((16, 16, 8))
+@pytest.mark.parametrize("emf", EMFS)
+def test_orszag_tang_half_turn_symmetry(emf):
+    s, V = W.orszag_tang_3d_ct((16, 16, 8), emf=emf)
     o = C.Oracle(s)
     U, _, _ = o.run(o.prim_to_cons(V), nsteps=20)
     R = U[:, :, ::-1, ::-1].copy()
@@ -98,18 +109,24 @@ def test_orszag_tang_half_turn_symmetry():
     assert (np.abs(U - R) / np.abs(U[9:]).max())[9:].max() <= 1e-12
 
 
-def test_cpa_3d_second_order():
+@pytest.mark.parametrize("emf", EMFS)
+def test_cpa_3d_second_order(emf):
     def err(n):
-        s, V = W.cpa_wave_3d_ct(n)
+        s, V = W.cpa_wave_3d_ct(n, emf=emf)
         o = C.Oracle(s)
         U, _, _ = o.run(o.prim_to_cons(V), t_end=s["period"])
         Vf = o.cons_to_prim(U)
         comps = [1, 2, 3, 5, 6, 7]
         return np.mean(np.abs(Vf[comps] - V[comps]))
 
-    e8, e16 = err(8), err(16)
-    assert math.log2(e8 / e16) >= 1.8, (e8, e16)
-    assert e16 <= 8e-3, e16
+    # the upwind EMF's minmod corner states clip the wave's extrema, so its
+    # error is larger and second order sets in on finer grids (measured
+    # orders 1.80 from 8^3 to 16^3, 1.94 from 16^3 to 32^3; mean EMF 1.96,
+    # 1.99)
+    n0, bar = (8, 8e-3) if emf == "mean" else (16, 3e-3)
+    e0, e1 = err(n0), err(2 * n0)
+    assert math.log2(e0 / e1) >= 1.8, (e0, e1)
+    assert e1 <= bar, e1
 
 
 def test_config_checks():
@@ -123,13 +140,14 @@ def test_config_checks():
         C.Oracle(s).prim_to_cons(V)  # GLM and CT together are refused
 
 
-def test_window_reproduces_full_grid_cell():
+@pytest.mark.parametrize("emf", EMFS)
+def test_window_reproduces_full_grid_cell(emf):
     """A WENO-Z SSP-RK3 step with constrained transport at a cell depends on
     cells within 9 along each axis: a periodic 21^3 window around the cell
     gives the full-grid value at its centre bit for bit, a 17^3 one does not.
     This is how the full-size parity test samples the oracle."""
     n = 32
-    s, V = W.orszag_tang_3d_ct(n)
+    s, V = W.orszag_tang_3d_ct(n, emf=emf)
     o = C.Oracle(s)
     U0 = o.prim_to_cons(V)
     dt, ch = o.cfl(U0)
@@ -139,7 +157,7 @@ def test_window_reproduces_full_grid_cell():
         sub = W.make_setup("window", 3, (2 * r + 1,) * 3, gamma=s["gamma"], cfl=s["cfl"],
                            riemann=s["riemann"], limiter="wenoz", time_order=3, glm=False,
                            hi=tuple((2 * r + 1) / n for _ in range(3)))
-        sub["ct"] = True
+        sub["ct"], sub["ct_emf"] = True, emf
         ow = C.Oracle(sub)
         worst = 0.0
         for (k, j, i) in cells:
@@ -147,3 +165,68 @@ def test_window_reproduces_full_grid_cell():
                          [(j + a) % n for a in range(-r, r + 1)], [(i + a) % n for a in range(-r, r + 1)])
             worst = max(worst, np.abs(ow.step(U0[idx], dt, ch, 1.0)[:, r, r, r] - full[:, k, j, i]).max())
         assert (worst == 0.0) == exact, (r, worst)
+
+
+def _minmod(a, b):
+    return np.where(a * b > 0, np.sign(a) * np.minimum(np.abs(a), np.abs(b)), 0.0)
+
+
+def test_upwind_emf_reduces_to_one_dimensional_hll_flux():
+    """Fields varying along x only (uniform face field b_x, so the face
+    divergence is zero; b_y, b_z, v, rho, p functions of x): the upwind EMFs
+    at the x faces are the one-dimensional HLL fluxes of the transverse
+    field, Ez = -F_x(B_y), Ey = F_x(B_z), with F(B_t) = v_x B_t - v_t B_x at
+    minmod-reconstructed face states and speed bounds a+ = max(0, v_x + c_f),
+    a- = max(0, c_f - v_x) over the face's two cells; Ex, whose plane holds
+    no variation, is the cell's own -(v_y B_z - v_z B_y)."""
+    nx, ny, nz = 16, 3, 4
+    s = W.make_setup("tube_ct", 3, (nx, ny, nz), gamma=5.0 / 3.0, cfl=0.3, glm=False)
+    s["ct"], s["ct_emf"] = True, "upwind"
+    x = (np.arange(nx) + 0.5) / nx
+    rng = np.random.default_rng(31)
+
+    def prof(a, b):
+        return (a + b * np.sin(2 * np.pi * x + rng.uniform(0, 6.3))
+                + 0.3 * b * np.sin(6 * np.pi * x + rng.uniform(0, 6.3)))
+
+    V = np.zeros((12, nz, ny, nx))
+    V[0] = prof(1.0, 0.3)
+    V[1], V[2], V[3] = prof(0.2, 0.5), prof(-0.1, 0.4), prof(0.05, 0.3)
+    V[4] = prof(1.0, 0.2)
+    bx = 0.7
+    V[9] = bx                                         # b_x at the x faces, uniform
+    V[10], V[11] = prof(0.3, 0.4), prof(-0.2, 0.3)    # b_y, b_z: functions of x
+    o = C.Oracle(s)
+    U = o.prim_to_cons(V)
+    E = o.ct_emf(U)
+    P = o.cons_to_prim(U)[:, 0, 0, :]   # cell primitives along x (cell B = face means)
+    by, bz = U[10, 0, 0, :], U[11, 0, 0, :]
+    cf = np.array([C.fast_speed(P[:9, i], s["gamma"], 0) for i in range(nx)])
+
+    def face_states(f):
+        # left state of face i - 1/2 from cell i - 1, right state from cell i
+        d = np.roll(f, -1) - f
+        sl = _minmod(np.roll(d, 1), d)
+        return np.roll(f + 0.5 * sl, 1), f - 0.5 * sl
+
+    vxL, vxR = face_states(P[1])
+    vyL, vyR = face_states(P[2])
+    vzL, vzR = face_states(P[3])
+    byL, byR = face_states(by)
+    bzL, bzR = face_states(bz)
+    vx = P[1]
+    ap = np.maximum(0.0, np.maximum(np.roll(vx + cf, 1), vx + cf))
+    am = np.maximum(0.0, np.maximum(np.roll(cf - vx, 1), cf - vx))
+
+    def hll(FL, FR, UL, UR):
+        return (ap * FL + am * FR - ap * am * (UR - UL)) / (ap + am)
+
+    Fby = hll(vxL * byL - vyL * bx, vxR * byR - vyR * bx, byL, byR)
+    Fbz = hll(vxL * bzL - vzL * bx, vxR * bzR - vzR * bx, bzL, bzR)
+    scale = np.abs(Fby).max() + np.abs(Fbz).max()
+    for j in range(ny):
+        for k in range(nz):
+            np.testing.assert_allclose(E[2, k, j, :], -Fby, rtol=0, atol=1e-14 * scale)
+            np.testing.assert_allclose(E[1, k, j, :], Fbz, rtol=0, atol=1e-14 * scale)
+            np.testing.assert_allclose(E[0, k, j, :], -(P[2] * bz - P[3] * by), rtol=0,
+                                       atol=1e-14 * scale)
