@@ -85,13 +85,13 @@ def measured_counters(kernel_key):
     return ent
 
 
-def run_gpu(n, dtype, steps, warmup, workload="turbulence", limiter="minmod", time_order=2):
+def run_gpu(n, dtype, steps, warmup, workload="turbulence", limiter="minmod", time_order=2, **gen_args):
     import torch
 
     from paper_2510_24175_amd import workloads
     from paper_2510_24175_amd.mhd import Context
 
-    setup, V = getattr(workloads, workload)(n)
+    setup, V = getattr(workloads, workload)(n, **gen_args)
     setup["limiter"], setup["time_order"] = limiter, time_order
     ctx = Context(setup, dtype)
     Vd = torch.from_numpy(V).cuda()
@@ -158,8 +158,14 @@ def run_gpu(n, dtype, steps, warmup, workload="turbulence", limiter="minmod", ti
     # stage), writes 3 faces and 3 cell-field components, and in the last
     # stage reads 6 components for the reductions (12 s | 15 s | 21 s):
     # 45 s, 57 s and 63 s B/cell for the first, a middle and the last stage.
+    # With the upwind EMF the stage kernel writes no fluxes (18 s | 27 s) and
+    # the EMF pass reads the input's 8 cell and 3 face components and writes
+    # 3 EMFs (14 s): 44 s, 56 s and 62 s.
     if setup.get("ct", False):
-        stages = [45] + [57] * (time_order - 2) + [63]
+        if setup.get("ct_emf") == "upwind":
+            stages = [44] + [56] * (time_order - 2) + [62]
+        else:
+            stages = [45] + [57] * (time_order - 2) + [63]
         res["alg_bytes_step"] = sum(stages) * s * ncell
     else:
         res["alg_bytes_step"] = (18 + 27 * (time_order - 1)) * s * ncell
@@ -336,7 +342,9 @@ def main():
                     help="comma list of paper-scheme runs (ot3d_f64, ot3d_f32, cpa3d_f64, cpa3d_f32)")
     ap.add_argument("--no-ct", action="store_true")
     ap.add_argument("--ct-n", type=int, default=352)
-    ap.add_argument("--ct-cases", default="f64,f32")
+    ap.add_argument("--ct-cases", default="f64,f32,f64_upwind",
+                    help="comma list of constrained-transport runs: f64, f32 (mean edge EMF), "
+                         "f64_upwind, f32_upwind (upwind edge EMF)")
     ap.add_argument("--cpu-configs", action="store_true",
                     help="only time the FP64 CPU oracle on the small configurations (no GPU)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -465,17 +473,18 @@ def main():
         # transport instead of GLM on its per-GPU share (704 x 704 x 352 per
         # four-GPU node, 352^3), 3D Orszag-Tang vortex
         cn = args.ct_n
-        cs = {"workload": f"3D Orszag-Tang vortex {cn}^3, WENO-Z + HLLD, constrained transport, SSP-RK3, "
-                          "CFL 0.3", "n": [cn] * 3}
-        for dt_ in [c.strip() for c in args.ct_cases.split(",") if c.strip()]:
+        cs = {"workload": f"3D Orszag-Tang vortex {cn}^3, WENO-Z + HLLD, constrained transport (mean edge "
+                          "EMF; _upwind: the upwind EMF), SSP-RK3, CFL 0.3", "n": [cn] * 3}
+        for key in [c.strip() for c in args.ct_cases.split(",") if c.strip()]:
+            dt_, _, emf = key.partition("_")
             r = run_gpu(cn, dt_, max(3, args.steps // 2), 2, workload="orszag_tang_3d_ct", limiter="wenoz",
-                        time_order=3)
-            cs[dt_] = {"value": round(r["mcells"], 2), "unit": "Mcell-updates/s",
+                        time_order=3, emf=emf or "mean")
+            cs[key] = {"value": round(r["mcells"], 2), "unit": "Mcell-updates/s",
                        "ms_per_step": round(r["ms_per_step"], 4),
                        "hbm_frac_step_algorithmic": round(r["hbm_frac_step"], 4),
                        "stage_ms": {"first_two": round(r["stage1_ms"], 4), "last": round(r["stage2_ms"], 4),
                                     "final_reduce": round(r["reduce_ms"], 4)}}
-            print(f"# constrained transport {dt_} {cn}^3: {r['ms_per_step']:.3f} ms/step", file=sys.stderr,
+            print(f"# constrained transport {key} {cn}^3: {r['ms_per_step']:.3f} ms/step", file=sys.stderr,
                   flush=True)
         out["constrained_transport"] = cs
     if not args.no_adjoint:

@@ -28,12 +28,16 @@
  *   - CFL: dt = C / max_{cells,d} (|v_d| + c_f,d)/dx_d and
  *     c_h = max_{cells,d} (|v_d| + c_f,d), reduced in FP64;
  *   - divergence control by constrained transport instead of GLM (the
- *     paper's weak-scaling runs; Evans & Hawley 1988) when ct = 1: the
+ *     paper's weak-scaling runs; Evans & Hawley 1988) when ct = 1 or 2: the
  *     field lives on the cell faces, each face's value is the normal field
- *     of its Riemann problem, edge EMFs are the arithmetic mean of the four
- *     face fluxes around the edge (Balsara & Spicer 1999), faces advance by
- *     the discrete curl of the EMFs with each Runge-Kutta stage, and the
- *     cell field is the mean of each cell's two faces along each axis.
+ *     of its Riemann problem, faces advance by the discrete curl of the edge
+ *     EMFs with each Runge-Kutta stage, and the cell field is the mean of
+ *     each cell's two faces along each axis.  Edge EMFs: ct = 1 the
+ *     arithmetic mean of the four face fluxes around the edge (Balsara &
+ *     Spicer 1999); ct = 2 the upwind EMF of Londrillo & Del Zanna (2004),
+ *     which the paper cites: the two-dimensional HLL average of the EMFs of
+ *     the four minmod-reconstructed states at the edge plus one HLL
+ *     dissipation term per transverse direction.
  * Magnetic pressure is |B|^2/2; ideal gas E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2
  * (psi is not part of E).  No density or pressure floors: a non-physical
  * state is reported as MHD_ERR_NONPHYSICAL.
@@ -111,7 +115,8 @@ typedef struct {
     double cfl;        /* Courant number C in (0, 1]                         */
     double glm_alpha;  /* GLM damping parameter alpha >= 0                   */
     int32_t time_order; /* 2: SSP-RK2, 3: SSP-RK3                            */
-    int32_t ct;        /* 1: constrained transport (3D, periodic, glm = 0)   */
+    int32_t ct;        /* 1, 2: constrained transport (3D, periodic, glm = 0) */
+                       /* with the mean (1) or upwind (2) edge EMF           */
 } mhd_config;
 
 /* Create a context for one grid on the current HIP device.
@@ -123,7 +128,7 @@ typedef struct {
  * hip_stream is a hipStream_t (NULL = the null stream).  Allocates the
  * library scratch (the only allocation besides mhd_timing_start).
  * Returns MHD_ERR_ARG for an invalid config (bad ndim, n, bounds, dtype,
- * solver, limiter, time_order, ct not 0 or 1, ct with glm = 1, mixed
+ * solver, limiter, time_order, ct not 0, 1 or 2, ct with glm = 1, mixed
  * periodic/outflow on one axis, gamma <= 1, cfl not in (0,1],
  * glm_alpha < 0), MHD_ERR_UNSUPPORTED for MHD_FLAG_ADJOINT with WENO-Z,
  * SSP-RK3 or ct = 1 and for ct = 1 on a grid that is not 3D and periodic,

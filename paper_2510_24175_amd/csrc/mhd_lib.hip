@@ -29,7 +29,8 @@ struct mhd_ctx {
     int ns = NQ;                 // state components (12 with constrained transport)
     void *u1_scratch = nullptr;  // stage-1 state when the caller passes none
     void *u2_scratch = nullptr;  // SSP-RK3 stage-2 state
-    void *ct_flx = nullptr;      // constrained transport: [6] transverse field fluxes
+    void *ct_flx = nullptr;      // constrained transport: [6] transverse field fluxes (mean EMF)
+                                 // or cell velocities and fast speeds (upwind EMF)
     void *ct_emf = nullptr;      // constrained transport: [3] edge EMFs
     double *part = nullptr;      // NPART x part_cap block partials
     int part_cap = 0;
@@ -208,9 +209,10 @@ mhd_status launch_step(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, do
 }
 
 // Constrained transport step (3D, periodic): per stage the stage kernel
-// (fluxes with the faces' normal field, transverse field fluxes to scratch,
-// cell update of rho, m, E), the edge EMFs, and the face update with the cell
-// field; the last face update reduces the CFL maxima and sums.
+// (fluxes with the faces' normal field, with the mean EMF the transverse
+// field fluxes to scratch, cell update of rho, m, E), the edge EMFs (mean of
+// those fluxes, or upwind from the stage's input state), and the face update
+// with the cell field; the last face update reduces the CFL maxima and sums.
 template <typename T, int SOLVER, int LIM>
 mhd_status launch_step_ct(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt, double ch, double damp)
 {
@@ -221,7 +223,7 @@ mhd_status launch_step_ct(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt,
     StageArgs<T> a;
     a.part = ctx->part;
     a.flag = ctx->flag;
-    a.flx = (T *)ctx->ct_flx;
+    a.flx = ctx->cfg.ct == 1 ? (T *)ctx->ct_flx : nullptr;  // the upwind EMF takes no fluxes
     a.nx = (int)ctx->n[0];
     a.ny = (int)ctx->n[1];
     a.nz = (int)ctx->n[2];
@@ -274,7 +276,16 @@ mhd_status launch_step_ct(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt,
         HIP_TRY(ctx, hipGetLastError());
         c.uin = uin;
         c.uout = uout;
-        hipLaunchKernelGGL(ct_emf_kernel<T>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, c);
+        if (ctx->cfg.ct == 2) {
+            // cell velocities and fast speeds into the flux scratch, which
+            // the upwind EMF leaves free, then the EMFs
+            hipLaunchKernelGGL(ct_cell_speeds_kernel<T>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, c,
+                               (T *)ctx->ct_flx);
+            HIP_TRY(ctx, hipGetLastError());
+            hipLaunchKernelGGL(ct_emf_upwind_kernel<T>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, c,
+                               (const T *)ctx->ct_flx);
+        } else
+            hipLaunchKernelGGL(ct_emf_kernel<T>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, c);
         HIP_TRY(ctx, hipGetLastError());
         hipLaunchKernelGGL((ct_face_kernel<T, KIND, last_stage(KIND)>), dim3(nb), dim3(RED_THREADS), 0,
                            ctx->stream, c);
@@ -501,7 +512,7 @@ mhd_status check_config(const mhd_config *c, const char *&why)
     if (c->limiter != MHD_MINMOD && c->limiter != MHD_MC && c->limiter != MHD_WENOZ)
         return why = "bad limiter", MHD_ERR_ARG;
     if (c->time_order != 2 && c->time_order != 3) return why = "time_order must be 2 or 3", MHD_ERR_ARG;
-    if (c->ct != 0 && c->ct != 1) return why = "ct must be 0 or 1", MHD_ERR_ARG;
+    if (c->ct < 0 || c->ct > 2) return why = "ct must be 0, 1 or 2", MHD_ERR_ARG;
     if (c->glm != 0 && c->glm != 1) return why = "glm must be 0 or 1", MHD_ERR_ARG;
     if ((c->flags & ~MHD_FLAG_ADJOINT) != 0) return why = "unknown flag bits", MHD_ERR_ARG;
     long long cells = 1;

@@ -41,9 +41,10 @@ template <typename T> struct StageArgs {
     const T *uin;   // state the fluxes are built from (Un or U1); with
                     // constrained transport its components 9..11 are the
                     // face field on each cell's lower x, y, z face
-    T *flx;         // constrained transport: [6][ncell] transverse field
-                    // fluxes of each cell's lower faces (x: By, Bz; y: Bx,
-                    // Bz; z: Bx, By)
+    T *flx;         // constrained transport with the mean edge EMF: [6][ncell]
+                    // transverse field fluxes of each cell's lower faces
+                    // (x: By, Bz; y: Bx, Bz; z: Bx, By); null with the
+                    // upwind EMF, which does not use them
     const T *un;    // Un (later stages' combine); equals uin in stage 1
     T *uout;        // this stage's output (U1, U2 or U_next)
     double *part;   // last stage: NPART x nblocks partials
@@ -311,7 +312,7 @@ stage_kernel(const StageArgs<T> a)
         T F[NQ];
         if constexpr (CT) {
             face_flux<T, SOLVER, true>(VL, VR, D, a.ph, F, a.uin[(9 + D) * a.ncell + fc]);
-            if (mine) {
+            if (mine && a.flx) {
                 a.flx[(2 * D) * a.ncell + fc] = F[D == 0 ? BY : BX];
                 a.flx[(2 * D + 1) * a.ncell + fc] = F[BZ];
             }
@@ -601,7 +602,7 @@ stage_kernel(const StageArgs<T> a)
                 if (CT && q >= BX && q <= BZ) continue;
                 __builtin_nontemporal_store(out[q], &a.uout[q * a.ncell + c]);  // not read again here
             }
-            if constexpr (CT) {
+            if (CT && a.flx) {
                 // transverse field fluxes of this cell's lower z face
                 a.flx[4 * a.ncell + c] = Fzm[BX];
                 a.flx[5 * a.ncell + c] = Fzm[BY];

@@ -117,8 +117,17 @@ def make_config(setup, dtype="f32", adjoint=False):
     c.cfl = float(setup["cfl"])
     c.glm_alpha = float(setup.get("glm_alpha", 0.1))
     c.time_order = int(setup.get("time_order", 2))
-    c.ct = 1 if setup.get("ct", False) else 0
+    c.ct = ct_mode(setup)
     return c
+
+
+def ct_mode(setup):
+    """mhd_config.ct of a setup: 0 without constrained transport, 1 with the
+    mean edge EMF, 2 with the upwind one (setup "ct_emf": "mean" or
+    "upwind")."""
+    if not setup.get("ct", False):
+        return 0
+    return {"mean": 1, "upwind": 2}[setup.get("ct_emf", "mean")]
 
 
 def step_noalloc(setup, dtype, Un, U_next, U1_out, dt, ch, damp, info=True, stream=None):

@@ -49,7 +49,7 @@ def _base():
 @pytest.mark.parametrize("field,value", [
     ("ndim", 0), ("ndim", 4), ("dtype", 7), ("riemann", 3), ("limiter", 9), ("glm", 2),
     ("flags", 2), ("gamma", 1.0), ("cfl", 0.0), ("cfl", 1.5), ("glm_alpha", -0.1),
-    ("limiter", 3), ("time_order", 1), ("time_order", 4), ("ct", 2),
+    ("limiter", 3), ("time_order", 1), ("time_order", 4), ("ct", 3), ("ct", -1),
 ])
 def test_invalid_config_is_rejected_before_device_use(field, value):
     cfg = _base()

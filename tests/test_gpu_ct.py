@@ -1,4 +1,6 @@
-"""GPU constrained transport against the FP64 CPU oracle, through the C ABI.
+"""GPU constrained transport against the FP64 CPU oracle, through the C ABI,
+with both edge EMFs: the arithmetic mean of the face fluxes and the upwind
+EMF of Londrillo & Del Zanna (2004).
 
 Bars as for the other parity tests: relative L1 per component (the 9 cell
 components and the 3 face components) <= 1e-10 with FP64 state and <= 1e-5
@@ -57,27 +59,33 @@ def _check(torch, name, s, V, dtype, nsteps):
     return ctx, o, Ug, Uo
 
 
+EMFS = ["mean", "upwind"]
+
+
+@pytest.mark.parametrize("emf", EMFS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("limiter,time_order", [("wenoz", 3), ("minmod", 2)])
-def test_orszag_tang_3d_ct(torch_cuda, dtype, limiter, time_order):
-    s, V = W.orszag_tang_3d_ct((70, 37, 19))
+def test_orszag_tang_3d_ct(torch_cuda, dtype, limiter, time_order, emf):
+    s, V = W.orszag_tang_3d_ct((70, 37, 19), emf=emf)
     s["limiter"], s["time_order"] = limiter, time_order
-    _check(torch_cuda, "orszag_tang_3d_ct", s, V, dtype, 20)
+    _check(torch_cuda, f"orszag_tang_3d_ct {emf}", s, V, dtype, 20)
 
 
+@pytest.mark.parametrize("emf", EMFS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("riemann", ["hlld", "hll"])
-def test_cpa_3d_ct(torch_cuda, dtype, riemann):
-    s, V = W.cpa_wave_3d_ct((34, 30, 36), riemann=riemann)
-    _check(torch_cuda, "cpa_3d_ct", s, V, dtype, 15)
+def test_cpa_3d_ct(torch_cuda, dtype, riemann, emf):
+    s, V = W.cpa_wave_3d_ct((34, 30, 36), riemann=riemann, emf=emf)
+    _check(torch_cuda, f"cpa_3d_ct {emf}", s, V, dtype, 15)
 
 
+@pytest.mark.parametrize("emf", EMFS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_ct_sums_and_cfl(torch_cuda, dtype):
+def test_ct_sums_and_cfl(torch_cuda, dtype, emf):
     # the reductions of the last face update against the oracle's
     torch = torch_cuda
     from paper_2510_24175_amd.mhd import Context
-    s, V = W.orszag_tang_3d_ct((40, 36, 20))
+    s, V = W.orszag_tang_3d_ct((40, 36, 20), emf=emf)
     ctx = Context(s, dtype)
     o = C.Oracle(s)
     Uo = o.prim_to_cons(V)
@@ -99,13 +107,14 @@ def test_ct_sums_and_cfl(torch_cuda, dtype):
     assert (np.abs(np.array(sums) - o.sums(Uo1))[:8] / scale[:8]).max() <= tol
 
 
+@pytest.mark.parametrize("emf", EMFS)
 @pytest.mark.parametrize("time_order", [2, 3])
-def test_ct_uniform_state(torch_cuda, time_order):
+def test_ct_uniform_state(torch_cuda, time_order, emf):
     torch = torch_cuda
     from paper_2510_24175_amd.mhd import Context
     from paper_2510_24175_amd.rollout import advance
     s, V = W.uniform((70, 9, 7), ndim=3)
-    s.update(ct=True, glm=False, limiter="wenoz", time_order=time_order)
+    s.update(ct=True, glm=False, limiter="wenoz", time_order=time_order, ct_emf=emf)
     W12 = np.zeros((12,) + V.shape[1:])
     W12[:9] = V
     W12[8] = 0.0
@@ -130,8 +139,9 @@ def _sample_cells_352(n, rng, count=24):
     return [(k, j, i) for (i, j, k) in cells]
 
 
+@pytest.mark.parametrize("emf", EMFS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_orszag_tang_3d_ct_352(torch_cuda, dtype):
+def test_orszag_tang_3d_ct_352(torch_cuda, dtype, emf):
     """The paper's weak-scaling configuration per GPU (704 x 704 x 352 per
     four-GPU node = 352^3), WENO-Z + HLLD + SSP-RK3 with constrained
     transport, in the launch configuration the bench times.  The first step
@@ -143,8 +153,8 @@ def test_orszag_tang_3d_ct_352(torch_cuda, dtype):
     torch = torch_cuda
     from paper_2510_24175_amd.mhd import Context
     n = 352
-    _say(f"[gpu-ct] Orszag-Tang 3D CT {n}^3 {dtype}")
-    s, V = W.orszag_tang_3d_ct(n)
+    _say(f"[gpu-ct] Orszag-Tang 3D CT {n}^3 {dtype} {emf} EMF")
+    s, V = W.orszag_tang_3d_ct(n, emf=emf)
     o = C.Oracle(s)
     Uo = o.prim_to_cons(V)
     dt, ch = o.cfl(Uo)
@@ -166,7 +176,7 @@ def test_orszag_tang_3d_ct_352(torch_cuda, dtype):
     sub = W.make_setup("window", 3, (2 * r + 1,) * 3, gamma=s["gamma"], cfl=s["cfl"],
                        riemann=s["riemann"], limiter="wenoz", time_order=3, glm=False,
                        hi=tuple((2 * r + 1) / n for _ in range(3)))
-    sub["ct"] = True
+    sub["ct"], sub["ct_emf"] = True, emf
     ow = C.Oracle(sub)
     rng = np.random.default_rng(12)
     comp_scale = np.maximum(np.abs(Uo).max(axis=(1, 2, 3)), 1e-2)
