@@ -23,7 +23,8 @@
 // (Un + U1 + dt L(U1)) / 2; 3 the SSP-RK3 stage 3/4 Un + 1/4 (U1 + dt L(U1));
 // 4 the SSP-RK3 result 1/3 Un + 2/3 (U2 + dt L(U2)).  The last stage of
 // either integrator damps psi and reduces on its output the CFL maxima and
-// the FP64 conservation sums into per-block partials.
+// the FP64 conservation sums into per-block partials (with helper waves,
+// the helpers take these reductions off the column owners).
 #pragma once
 
 #include <type_traits>
@@ -161,8 +162,9 @@ __device__ __forceinline__ double wave_max(double v)
 // faster than at one wave per SIMD without spills).  FP64 WENO-Z: 2 (140 KB
 // of LDS, the fluxes laid over the primitive plane, allows one workgroup per
 // compute unit: 4 rows with two waves each, the helper waves below; 256
-// registers, some spilled: the 416^3 SSP-RK3 step runs in 50.5 ms against
-// 58.8 ms with one 4-wave workgroup at 512 registers).
+// registers, some spilled: the 416^3 SSP-RK3 step ran 14% faster than with
+// one 4-wave workgroup at 512 registers, before the last stage's reductions
+// moved to the helpers).
 template <typename T, int LIM> constexpr int stage_min_waves()
 {
     return sizeof(T) == 4 ? (LIM == LIM_WENOZ ? 2 : 3) : 2;
@@ -230,7 +232,17 @@ stage_kernel(const StageArgs<T> a)
     constexpr int OFY = OFX + SZFX;
     constexpr int OEX = ALIAS ? (SZP > SZFX + SZFY ? SZP : SZFX + SZFY) : OFY + SZFY;
     constexpr int OEY = OEX + SZEX;
-    constexpr int SZL = OEY + SZEY;
+    constexpr int SZL0 = OEY + SZEY;
+    // Last stage with helper waves: the column owners leave each plane's
+    // results in LDS (OUTS[NQ][TY * TX]) and the helpers take their FP64
+    // sums and signal speeds during the next plane's z-face phase, which
+    // is the owners' alone; the owners then carry no reduction state
+    // through the march.
+    constexpr bool HELP_RED = LAST && stage_row_waves<T, LIM>() > 1;
+    static_assert(!HELP_RED || sizeof(T) == 8, "helper reductions keep FP64 sums in T registers");
+    constexpr int OOUT = SZL0;
+    constexpr int SZL = OOUT + (HELP_RED ? NQ * TY * TX : 0);
+    static_assert(SZL * (int)sizeof(T) <= 160 * 1024, "LDS of one compute unit");
 
     __shared__ T lds[SZL];
     T *const P = lds;
@@ -238,6 +250,7 @@ stage_kernel(const StageArgs<T> a)
     T *const FYs = lds + OFY;
     T *const EX = lds + OEX;
     T *const EY = lds + OEY;
+    T *const OUTS = lds + OOUT;
 
     const int t = threadIdx.x;
     const int tx = t & (TX - 1);
@@ -353,6 +366,30 @@ stage_kernel(const StageArgs<T> a)
     constexpr int ZW = WENO ? 4 : 2;
     constexpr int ZC = WENO ? 1 : 0;       // window slot of plane k
     T Wz[ZW][NQ], D0[NQ], ZT[NQ], Fzm[NQ];
+    // A helper wave keeps its running FP64 sums of the cells its row's owner
+    // left in OUTS (same column) in Fzm and its maxima of the signal speeds
+    // in ZT[0..1]: registers the owners hold through the march anyway and
+    // the helpers have no other use for.  Cells outside the grid count
+    // nothing.
+    auto helper_fold = [&]() {
+        const int row = wave - TY;
+        if ((i < a.nx) & (j0 + row < a.ny)) {
+            T u[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                u[q] = OUTS[q * TY * TX + row * TX + tx];
+                Fzm[q] += u[q];
+            }
+            double smx = ZT[0], cmx = ZT[1];
+            ok &= cell_speeds<T, NDIM>(u, a.gamma_d, a.idx_d, smx, cmx);
+            ZT[0] = smx;
+            ZT[1] = cmx;
+        }
+    };
+    if (HELP_RED && !owner) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) Fzm[q] = ZT[q] = T(0);
+    }
     if (NDIM == 3 && owner) {
         T VL[NQ], VR[NQ];
         if constexpr (WENO) {
@@ -396,16 +433,16 @@ stage_kernel(const StageArgs<T> a)
     // estimates of the two maxima (their FP64 speeds are taken at the end)
     float best_s = -1.0f, best_c = -1.0f;
     int k_s = -1, k_c = -1;
-    double sum[NQ];
+    double sum[HELP_RED ? 1 : NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) sum[q] = 0.0;
+    for (int q = 0; q < (HELP_RED ? 1 : NQ); ++q) sum[q] = 0.0;
 
     // The stage combine's inputs at the thread's own cell are loaded at the
     // top of the plane, so that their latency hides behind the face phases,
     // where registers allow: FP32 PLM (measured 2% faster).  FP64 PLM would
     // spill (25% slower), FP32 WENO-Z runs at two waves per SIMD (3% slower),
-    // and FP64 WENO-Z with its helper waves spills 2.2x more (416^3 step 50.5
-    // against 78.5 ms); those load them at the update.
+    // and FP64 WENO-Z with its helper waves spills 2.2x more (the 416^3 step
+    // 55% slower); those load them at the update.
     constexpr bool PREFETCH = (sizeof(T) == 4) && !WENO;
     auto load_combine = [&](long long c, T *cin, T *cun) {
 #pragma unroll
@@ -419,8 +456,12 @@ stage_kernel(const StageArgs<T> a)
         const long long zk = zoff(k);
         T cin[NQ], cun[NQ];
         if (PREFETCH && active) load_combine(zk + own, cin, cun);
-        // the fluxes of the previous plane sit where P goes
-        if (ALIAS && k > k0) __syncthreads();
+        // the fluxes of the previous plane sit where P goes; the helpers
+        // read the previous plane's results
+        if ((ALIAS || HELP_RED) && k > k0) __syncthreads();
+        // (the results stay until the next plane's update, several
+        // barriers on)
+        if (HELP_RED && !owner && k > k0) helper_fold();
         // (a) primitives of plane k into LDS: own column and halo cell
         if (owner) {
 #pragma unroll
@@ -607,7 +648,10 @@ stage_kernel(const StageArgs<T> a)
                 a.flx[4 * a.ncell + c] = Fzm[BX];
                 a.flx[5 * a.ncell + c] = Fzm[BY];
             }
-            if (LAST) {
+            if constexpr (HELP_RED) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) OUTS[q * TY * TX + t] = out[q];
+            } else if (LAST) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) sum[q] += (double)out[q];
                 if constexpr (sizeof(T) == 8) {
@@ -645,20 +689,28 @@ stage_kernel(const StageArgs<T> a)
             ok &= cell_speeds<T, NDIM>(u, a.gamma_d, a.idx_d, smax, cmax);
         }
     }
-    if (!ok) atomicOr(a.flag, 1);
-
     if (LAST) {
         // block reduction of the partials in a fixed order
         __syncthreads();
         double *red = reinterpret_cast<double *>(P);  // LDS reuse, TY * NPART doubles
         double vals[NPART];
-        vals[0] = wave_max(smax);
-        vals[1] = wave_max(cmax);
+        if constexpr (HELP_RED) {
+            if (!owner) helper_fold();  // the chunk's last plane
+            vals[0] = wave_max(ZT[0]);
+            vals[1] = wave_max(ZT[1]);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) vals[2 + q] = wave_sum(sum[q]);
-        if (tx == 0 && owner) {
+            for (int q = 0; q < NQ; ++q) vals[2 + q] = wave_sum(Fzm[q]);
+        } else {
+            vals[0] = wave_max(smax);
+            vals[1] = wave_max(cmax);
 #pragma unroll
-            for (int e = 0; e < NPART; ++e) red[ty * NPART + e] = vals[e];
+            for (int q = 0; q < NQ; ++q) vals[2 + q] = wave_sum(sum[q]);
+        }
+        // the row's reducing wave: its helper, or its owner
+        if (tx == 0 && (HELP_RED ? !owner : owner)) {
+            const int row = HELP_RED ? wave - TY : ty;
+#pragma unroll
+            for (int e = 0; e < NPART; ++e) red[row * NPART + e] = vals[e];
         }
         __syncthreads();
         if (t < NPART) {
@@ -670,6 +722,7 @@ stage_kernel(const StageArgs<T> a)
             a.part[(long long)t * a.nblocks + lb] = r;
         }
     }
+    if (!ok) atomicOr(a.flag, 1);
 }
 
 } // namespace mhd
