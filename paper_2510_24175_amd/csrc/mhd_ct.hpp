@@ -13,7 +13,9 @@
 // (x: By, Bz; y: Bx, Bz; z: Bx, By); emf_kernel forms the EMFs on each cell's
 // lower edges (Ex at (j-1/2, k-1/2), Ey at (i-1/2, k-1/2), Ez at
 // (i-1/2, j-1/2)); face_kernel applies dB/dt = -curl E.  Both are
-// element-wise passes (HBM-bound, no LDS) over a grid-stride range.
+// element-wise passes (HBM-bound, no LDS) over a grid-stride range.  The
+// upwind EMF instead takes the stage's input state itself (the stage kernel
+// then stores no fluxes) in a z-marching tiled pass.
 #pragma once
 
 #include "mhd_reduce.hpp"
@@ -69,35 +71,28 @@ __global__ void __launch_bounds__(RED_THREADS) ct_emf_kernel(const CTArgs<T> a)
     }
 }
 
-// Per-cell inputs of the upwind EMF, from the stage's input state: velocity
-// (3) and fast magnetosonic speed along each axis (3), to w[6][ncell].
+// Velocity (3) and fast magnetosonic speed along each axis (3) of cell c
+// of the conserved state u (cell-centred field), for the upwind EMF.
 template <typename T>
-__global__ void __launch_bounds__(RED_THREADS) ct_cell_speeds_kernel(const CTArgs<T> a, T *w)
+__device__ __forceinline__ void ct_cell_vc(const T *__restrict__ u, long long nc, long long c, T gamma, T gm1,
+                                           T *v, T *cf)
 {
-    const long long nc = a.ncell;
-    const T gamma = (T)a.gamma_d, gm1 = (T)(a.gamma_d - 1.0);
-    for (long long c = (long long)blockIdx.x * RED_THREADS + threadIdx.x; c < nc;
-         c += (long long)gridDim.x * RED_THREADS) {
-        const T rho = a.uin[c], ir = Num<T>::rcp(rho);
-        const T m[3] = {a.uin[nc + c], a.uin[2 * nc + c], a.uin[3 * nc + c]};
-        const T b[3] = {a.uin[5 * nc + c], a.uin[6 * nc + c], a.uin[7 * nc + c]};
-        const T bsq = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-        const T pr = gm1 * (a.uin[4 * nc + c] - T(0.5) * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * ir -
-                            T(0.5) * bsq);
+    const T rho = u[c], ir = Num<T>::rcp(rho);
+    const T m[3] = {u[nc + c], u[2 * nc + c], u[3 * nc + c]};
+    const T b[3] = {u[5 * nc + c], u[6 * nc + c], u[7 * nc + c]};
+    const T bsq = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    const T pr = gm1 * (u[4 * nc + c] - T(0.5) * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * ir - T(0.5) * bsq);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            w[(long long)d * nc + c] = m[d] * ir;
-            w[(long long)(3 + d) * nc + c] = fast_speed(rho, pr, bsq, b[d] * b[d], gamma, ir);
-        }
+    for (int d = 0; d < 3; ++d) {
+        v[d] = m[d] * ir;
+        cf[d] = fast_speed(rho, pr, bsq, b[d] * b[d], gamma, ir);
     }
 }
 
-// Upwind edge EMFs (upwind constrained transport of Londrillo & Del Zanna
-// 2004, HLL averaging), on each cell's lower edges, from the cells'
-// velocities and fast speeds (w, ct_cell_speeds_kernel) and the face field
-// of the stage's input state.  For the EMF along axis e, with (e, p, q)
-// cyclic, four cells meet at the edge: the lower or upper one along p
-// (a = 0, 1) and along q (b = 0, 1).  Each gives a state at the edge:
+// Upwind EMF (upwind constrained transport of Londrillo & Del Zanna 2004,
+// HLL averaging) of one edge along axis e, with (e, p, q) cyclic.  Four
+// cells meet at the edge: the lower or upper one along p (a = 0, 1) and
+// along q (b = 0, 1).  Each gives a state at the edge:
 //   v^ab  = cell velocity + (1/2 - a) s_p(v) + (1/2 - b) s_q(v),
 //   B_q^a = q-face field on side a + (1/2 - a) s_p(B_q),
 //   B_p^b = p-face field on side b + (1/2 - b) s_q(B_p),
@@ -109,90 +104,235 @@ __global__ void __launch_bounds__(RED_THREADS) ct_cell_speeds_kernel(const CTArg
 // w_p^0 = a_p+ / (a_p+ + a_p-), w_p^1 = a_p- / (a_p+ + a_p-): the HLL flux of
 // B_q along p (F_p(B_q) = -E_e) and of B_p along q (F_q(B_p) = E_e); where
 // the fields vary along p alone it is the one-dimensional HLL flux of B_q.
-// Each thread reads the velocities of the 12 cells of the 4 x 4 block around
-// an edge (corners left out) for the states and their slopes.
+// Inputs: vp, vq the p and q velocity components of the 4 x 4 cell block
+// [mp][mq], mp, mq = 0..3 for offsets -2..1 along p and q from the upper
+// cell of the edge (corners unused); cp, cq the fast speeds along p and q
+// of its four cells (mp, mq = 1, 2); fq[m] the q-face field of the cells at
+// p offset m - 2, on the edge's q plane; fp[m] the p-face field of the
+// cells at q offset m - 2.
 template <typename T>
-__global__ void __launch_bounds__(RED_THREADS) ct_emf_upwind_kernel(const CTArgs<T> a, const T *w)
+__device__ __forceinline__ T ct_upwind_edge(const T (&vp)[4][4], const T (&vq)[4][4], const T (&cp)[4][4],
+                                            const T (&cq)[4][4], const T (&fq)[4], const T (&fp)[4])
 {
-    const long long nxy = (long long)a.nx * a.ny, nc = a.ncell;
-    const int n3[3] = {a.nx, a.ny, a.nz};
-    const long long st[3] = {1, a.nx, nxy};
-    for (long long c = (long long)blockIdx.x * RED_THREADS + threadIdx.x; c < nc;
-         c += (long long)gridDim.x * RED_THREADS) {
-        int co[3];
-        ct_coords(c, a.nx, a.ny, co[0], co[1], co[2]);
-        // offset of the cell m = -2 .. 1 steps away along each axis (periodic)
-        long long off[3][4];
+    T ev[2][2][2];  // edge velocities (p, q components) from cell (a, b)
+    T app = T(0), apm = T(0), aqp = T(0), aqm = T(0);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
+    for (int ca = 0; ca < 2; ++ca) {
 #pragma unroll
-            for (int m = -2; m <= 1; ++m) off[d][m + 2] = (long long)(ct_wrap(co[d] + m, n3[d]) - co[d]) * st[d];
+        for (int cb = 0; cb < 2; ++cb) {
+            const int mp = ca + 1, mq = cb + 1;  // block index of the cell
+            const T hp = T(0.5) - T(ca), hq = T(0.5) - T(cb);
+            const T spp = Num<T>::minmod(vp[mp][mq] - vp[mp - 1][mq], vp[mp + 1][mq] - vp[mp][mq]);
+            const T sqp = Num<T>::minmod(vp[mp][mq] - vp[mp][mq - 1], vp[mp][mq + 1] - vp[mp][mq]);
+            const T spq = Num<T>::minmod(vq[mp][mq] - vq[mp - 1][mq], vq[mp + 1][mq] - vq[mp][mq]);
+            const T sqq = Num<T>::minmod(vq[mp][mq] - vq[mp][mq - 1], vq[mp][mq + 1] - vq[mp][mq]);
+            ev[ca][cb][0] = vp[mp][mq] + hp * spp + hq * sqp;
+            ev[ca][cb][1] = vq[mp][mq] + hp * spq + hq * sqq;
+            app = Num<T>::max(app, vp[mp][mq] + cp[mp][mq]);
+            apm = Num<T>::max(apm, cp[mp][mq] - vp[mp][mq]);
+            aqp = Num<T>::max(aqp, vq[mp][mq] + cq[mp][mq]);
+            aqm = Num<T>::max(aqm, cq[mp][mq] - vq[mp][mq]);
         }
+    }
+    // face fields at the edge, reconstructed along p (B_q) and q (B_p)
+    T Bq[2], Bp[2];
 #pragma unroll
-        for (int e = 0; e < 3; ++e) {
-            const int p = (e + 1) % 3, q = (e + 2) % 3;
-            const T *vpa = w + (long long)p * nc, *vqa = w + (long long)q * nc;
-            const T *cpa = w + (long long)(3 + p) * nc, *cqa = w + (long long)(3 + q) * nc;
-            // velocities along p and q of the 4 x 4 block (mp, mq) in -2 .. 1
-            T vp[4][4], vq[4][4];
+    for (int s2 = 0; s2 < 2; ++s2) {
+        const T h = T(0.5) - T(s2);
+        const T f0 = fq[s2 + 1];
+        Bq[s2] = f0 + h * Num<T>::minmod(f0 - fq[s2], fq[s2 + 2] - f0);
+        const T g0 = fp[s2 + 1];
+        Bp[s2] = g0 + h * Num<T>::minmod(g0 - fp[s2], fp[s2 + 2] - g0);
+    }
+    const T isp = Num<T>::rcp(app + apm), isq = Num<T>::rcp(aqp + aqm);
+    const T wp[2] = {app * isp, apm * isp}, wq[2] = {aqp * isq, aqm * isq};
+    T Em = T(0);
+#pragma unroll
+    for (int ca = 0; ca < 2; ++ca) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) Em += wp[ca] * wq[cb] * (ev[ca][cb][1] * Bp[cb] - ev[ca][cb][0] * Bq[ca]);
+    }
+    Em += app * apm * isp * (Bq[1] - Bq[0]) - aqp * aqm * isq * (Bp[1] - Bp[0]);
+    return Em;
+}
+
+// Tiling of the upwind EMF pass: TX x TY column tiles, z chunks of kz planes.
+struct CTTiles {
+    int tiles_x, tiles_y, kz, nblocks;
+};
+
+// Upwind edge EMFs on each cell's lower edges (Ex at (j-1/2, k-1/2), Ey at
+// (i-1/2, k-1/2), Ez at (i-1/2, j-1/2)), from the stage's input state.  A
+// workgroup owns a tile of TX x TY columns (one thread per column) and
+// marches along z over a chunk of planes.  The 4 x 4 blocks of the three
+// edges of a cell span planes k-2 .. k+1 and, in each, rows and columns -2
+// .. 1 around it: every plane's velocities and fast speeds are formed once
+// per tile (with that halo) into LDS rings, velocities for planes k-2 ..
+// k+1 and fast speeds for k-1 .. k+1 (one plane ahead, formed with the
+// velocities), so that a plane's cells are converted once per tile instead
+// of once per use.  The face field is read from global memory: its
+// in-plane neighbours at plane k, and the cell's own x and y faces at planes
+// k-2 .. k+1 from a register window slid with the march.
+template <typename T, int TY>
+__global__ void __launch_bounds__(TX *TY) ct_emf_upwind_kernel(const CTArgs<T> a, const CTTiles g)
+{
+    constexpr int PX = TX + 3, PY = TY + 3, PL = PX * PY;  // LDS plane: columns -2 .. TX, rows -2 .. TY
+    constexpr int NT = TX * TY;
+    constexpr int NIT = (PL + NT - 1) / NT;  // plane cells per thread
+    __shared__ T Vr[4][3][PL];  // velocities; plane p in slot (p + 8) & 3
+    __shared__ T Cr[3][3][PL];  // fast speeds; plane p in slot (p + 9) % 3
+
+    const int t = threadIdx.x, tx = t % TX, ty = t / TX;
+    const int lb = logical_block(blockIdx.x, g.nblocks);
+    const int tile_x = lb % g.tiles_x, rest = lb / g.tiles_x;
+    const int tile_y = rest % g.tiles_y, chunk = rest / g.tiles_y;
+    const int i0 = tile_x * TX, j0 = tile_y * TY;
+    const int k0 = chunk * g.kz, k1 = min(k0 + g.kz, a.nz);
+    const long long nc = a.ncell, nxy = (long long)a.nx * a.ny;
+    const T gamma = (T)a.gamma_d, gm1 = (T)(a.gamma_d - 1.0);
+
+    // in-plane index of this thread's LDS plane cells (periodic images)
+    int ioff[NIT];
+#pragma unroll
+    for (int m = 0; m < NIT; ++m) {
+        const int it = t + m * NT;
+        ioff[m] = 0;
+        if (it < PL) {
+            const int ly = it / PX, lx = it - ly * PX;
+            const int gi = ((i0 + lx - 2) % a.nx + a.nx) % a.nx;
+            const int gj = ((j0 + ly - 2) % a.ny + a.ny) % a.ny;
+            ioff[m] = gj * a.nx + gi;
+        }
+    }
+    // velocities and fast speeds of plane p (-2 <= p <= nz) into the rings
+    auto load_plane = [&](int p) {
+        const long long zo = (long long)ct_wrap(p, a.nz) * nxy;
+        const int sv = (p + 8) & 3, sc = (p + 9) % 3;
+#pragma unroll
+        for (int m = 0; m < NIT; ++m) {
+            const int it = t + m * NT;
+            if (it < PL) {
+                T v[3], cf[3];
+                ct_cell_vc(a.uin, nc, zo + ioff[m], gamma, gm1, v, cf);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    Vr[sv][d][it] = v[d];
+                    Cr[sc][d][it] = cf[d];
+                }
+            }
+        }
+    };
+
+    const int i = i0 + tx, j = j0 + ty;
+    const bool active = (i < a.nx) & (j < a.ny);
+    const int ic = active ? i : 0, jc = active ? j : 0;
+    const long long col = (long long)jc * a.nx + ic;
+    int ox[4], oy[4];  // offsets of the x and y neighbours -2 .. 1 (periodic)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        ox[m] = ct_wrap(ic + m - 2, a.nx) - ic;
+        oy[m] = (ct_wrap(jc + m - 2, a.ny) - jc) * a.nx;
+    }
+    const int base = (ty + 2) * PX + tx + 2;  // the cell in an LDS plane
+    const T *bxg = a.uin + 9 * nc, *byg = a.uin + 10 * nc, *bzg = a.uin + 11 * nc;
+    T bxw[4], byw[4];  // own x and y faces at planes k-2 .. k+1
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const long long zo = (long long)ct_wrap(k0 + m - 2, a.nz) * nxy;
+        bxw[m] = bxg[zo + col];
+        byw[m] = byg[zo + col];
+    }
+    for (int p = k0 - 2; p <= k0 + 1; ++p) load_plane(p);
+    __syncthreads();
+
+    for (int k = k0; k < k1; ++k) {
+        if (active) {
+            const long long c = (long long)k * nxy + col;
+            const int sv[4] = {(k + 6) & 3, (k + 7) & 3, (k + 8) & 3, (k + 9) & 3};  // planes k-2 .. k+1
+            const int sc[2] = {(k + 8) % 3, (k + 9) % 3};                          // planes k-1, k
+            T vp[4][4], vq[4][4], cp[4][4], cq[4][4], fq[4], fp[4];
+            auto corner = [](int mp, int mq) { return (mp == 0 || mp == 3) && (mq == 0 || mq == 3); };
+            // Ex: p = y, q = z
 #pragma unroll
             for (int mp = 0; mp < 4; ++mp) {
 #pragma unroll
                 for (int mq = 0; mq < 4; ++mq) {
-                    vp[mp][mq] = vq[mp][mq] = T(0);
-                    if ((mp == 0 || mp == 3) && (mq == 0 || mq == 3)) continue;  // corners: not used
-                    const long long x = c + off[p][mp] + off[q][mq];
-                    vp[mp][mq] = vpa[x];
-                    vq[mp][mq] = vqa[x];
+                    vp[mp][mq] = vq[mp][mq] = cp[mp][mq] = cq[mp][mq] = T(0);
+                    if (corner(mp, mq)) continue;
+                    const int x = base + (mp - 2) * PX;
+                    vp[mp][mq] = Vr[sv[mq]][1][x];
+                    vq[mp][mq] = Vr[sv[mq]][2][x];
+                    if (mp >= 1 && mp <= 2 && mq >= 1 && mq <= 2) {
+                        cp[mp][mq] = Cr[sc[mq - 1]][1][x];
+                        cq[mp][mq] = Cr[sc[mq - 1]][2][x];
+                    }
                 }
             }
-            T ev[2][2][2];  // corner velocities (p, q components) of cell (a, b)
-            T app = T(0), apm = T(0), aqp = T(0), aqm = T(0);
 #pragma unroll
-            for (int ca = 0; ca < 2; ++ca) {
+            for (int m = 0; m < 4; ++m) {
+                fq[m] = bzg[c + oy[m]];
+                fp[m] = byw[m];
+            }
+            a.emf[c] = ct_upwind_edge(vp, vq, cp, cq, fq, fp);
+            // Ey: p = z, q = x
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    const int mp = ca + 1, mq = cb + 1;  // block index of the cell
-                    const T hp = T(0.5) - T(ca), hq = T(0.5) - T(cb);
-                    const T spp = Num<T>::minmod(vp[mp][mq] - vp[mp - 1][mq], vp[mp + 1][mq] - vp[mp][mq]);
-                    const T sqp = Num<T>::minmod(vp[mp][mq] - vp[mp][mq - 1], vp[mp][mq + 1] - vp[mp][mq]);
-                    const T spq = Num<T>::minmod(vq[mp][mq] - vq[mp - 1][mq], vq[mp + 1][mq] - vq[mp][mq]);
-                    const T sqq = Num<T>::minmod(vq[mp][mq] - vq[mp][mq - 1], vq[mp][mq + 1] - vq[mp][mq]);
-                    ev[ca][cb][0] = vp[mp][mq] + hp * spp + hq * sqp;
-                    ev[ca][cb][1] = vq[mp][mq] + hp * spq + hq * sqq;
-                    const long long x = c + off[p][mp] + off[q][mq];
-                    const T cp = cpa[x], cq = cqa[x];
-                    app = Num<T>::max(app, vp[mp][mq] + cp);
-                    apm = Num<T>::max(apm, cp - vp[mp][mq]);
-                    aqp = Num<T>::max(aqp, vq[mp][mq] + cq);
-                    aqm = Num<T>::max(aqm, cq - vq[mp][mq]);
+            for (int mp = 0; mp < 4; ++mp) {
+#pragma unroll
+                for (int mq = 0; mq < 4; ++mq) {
+                    vp[mp][mq] = vq[mp][mq] = cp[mp][mq] = cq[mp][mq] = T(0);
+                    if (corner(mp, mq)) continue;
+                    const int x = base + mq - 2;
+                    vp[mp][mq] = Vr[sv[mp]][2][x];
+                    vq[mp][mq] = Vr[sv[mp]][0][x];
+                    if (mp >= 1 && mp <= 2 && mq >= 1 && mq <= 2) {
+                        cp[mp][mq] = Cr[sc[mp - 1]][2][x];
+                        cq[mp][mq] = Cr[sc[mp - 1]][0][x];
+                    }
                 }
             }
-            // face fields at the edge: the q faces of the cells on either side
-            // along p, reconstructed along p; the p faces on either side along
-            // q, reconstructed along q
-            T Bq[2], Bp[2];
 #pragma unroll
-            for (int s2 = 0; s2 < 2; ++s2) {
-                const T h = T(0.5) - T(s2);
-                const T *fq = a.uin + (long long)(9 + q) * nc;
-                const T f0 = fq[c + off[p][s2 + 1]];
-                Bq[s2] = f0 + h * Num<T>::minmod(f0 - fq[c + off[p][s2]], fq[c + off[p][s2 + 2]] - f0);
-                const T *fp = a.uin + (long long)(9 + p) * nc;
-                const T g0 = fp[c + off[q][s2 + 1]];
-                Bp[s2] = g0 + h * Num<T>::minmod(g0 - fp[c + off[q][s2]], fp[c + off[q][s2 + 2]] - g0);
+            for (int m = 0; m < 4; ++m) {
+                fq[m] = bxw[m];
+                fp[m] = bzg[c + ox[m]];
             }
-            const T isp = Num<T>::rcp(app + apm), isq = Num<T>::rcp(aqp + aqm);
-            const T wp[2] = {app * isp, apm * isp}, wq[2] = {aqp * isq, aqm * isq};
-            T Em = T(0);
+            a.emf[nc + c] = ct_upwind_edge(vp, vq, cp, cq, fq, fp);
+            // Ez: p = x, q = y
 #pragma unroll
-            for (int ca = 0; ca < 2; ++ca) {
+            for (int mp = 0; mp < 4; ++mp) {
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-                    Em += wp[ca] * wq[cb] * (ev[ca][cb][1] * Bp[cb] - ev[ca][cb][0] * Bq[ca]);
+                for (int mq = 0; mq < 4; ++mq) {
+                    vp[mp][mq] = vq[mp][mq] = cp[mp][mq] = cq[mp][mq] = T(0);
+                    if (corner(mp, mq)) continue;
+                    const int x = base + (mp - 2) + (mq - 2) * PX;
+                    vp[mp][mq] = Vr[sv[2]][0][x];
+                    vq[mp][mq] = Vr[sv[2]][1][x];
+                    if (mp >= 1 && mp <= 2 && mq >= 1 && mq <= 2) {
+                        cp[mp][mq] = Cr[sc[1]][0][x];
+                        cq[mp][mq] = Cr[sc[1]][1][x];
+                    }
+                }
             }
-            Em += app * apm * isp * (Bq[1] - Bq[0]) - aqp * aqm * isq * (Bp[1] - Bp[0]);
-            a.emf[(long long)e * nc + c] = Em;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                fq[m] = byg[c + ox[m]];
+                fp[m] = bxg[c + oy[m]];
+            }
+            a.emf[2 * nc + c] = ct_upwind_edge(vp, vq, cp, cq, fq, fp);
+        }
+        if (k + 1 < k1) {
+            // plane k+2 goes where plane k-2 (velocities) and k-1 (fast
+            // speeds) were
+            __syncthreads();
+            load_plane(k + 2);
+            const long long zo = (long long)ct_wrap(k + 2, a.nz) * nxy;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                bxw[m] = bxw[m + 1];
+                byw[m] = byw[m + 1];
+            }
+            bxw[3] = bxg[zo + col];
+            byw[3] = byg[zo + col];
+            __syncthreads();
         }
     }
 }

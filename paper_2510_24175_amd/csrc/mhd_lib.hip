@@ -53,6 +53,9 @@ struct mhd_ctx {
 namespace {
 
 constexpr int CFL_MAX_BLOCKS = 4096;
+// rows of an upwind EMF tile (TX x 8 columns: 124 KB of LDS in FP64, one
+// workgroup of 8 waves per compute unit; 62 KB in FP32, two)
+constexpr int CT_EMF_TY = 8;
 
 mhd_status fail(mhd_ctx *ctx, mhd_status st, const char *msg)
 {
@@ -261,6 +264,14 @@ mhd_status launch_step_ct(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt,
     c.gamma_d = ctx->cfg.gamma;
     const int nb = (int)std::min<long long>((ctx->ncell + RED_THREADS - 1) / RED_THREADS, CFL_MAX_BLOCKS);
     c.nblocks = nb;
+    // upwind EMF tiling: z chunks of up to 32 planes, shortened until the
+    // pass has eight workgroups per compute unit
+    CTTiles ug;
+    ug.tiles_x = (a.nx + TX - 1) / TX;
+    ug.tiles_y = (a.ny + CT_EMF_TY - 1) / CT_EMF_TY;
+    ug.kz = 32;
+    while (ug.kz > 4 && (long long)ug.tiles_x * ug.tiles_y * ((a.nz + ug.kz - 1) / ug.kz) < 8 * 256) ug.kz >>= 1;
+    ug.nblocks = ug.tiles_x * ug.tiles_y * ((a.nz + ug.kz - 1) / ug.kz);
 
     hipEvent_t *ev = nullptr;
     if (ctx->timed_steps < ctx->timed_cap) ev = &ctx->events[4 * ctx->timed_steps++];
@@ -276,15 +287,10 @@ mhd_status launch_step_ct(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt,
         HIP_TRY(ctx, hipGetLastError());
         c.uin = uin;
         c.uout = uout;
-        if (ctx->cfg.ct == 2) {
-            // cell velocities and fast speeds into the flux scratch, which
-            // the upwind EMF leaves free, then the EMFs
-            hipLaunchKernelGGL(ct_cell_speeds_kernel<T>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, c,
-                               (T *)ctx->ct_flx);
-            HIP_TRY(ctx, hipGetLastError());
-            hipLaunchKernelGGL(ct_emf_upwind_kernel<T>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, c,
-                               (const T *)ctx->ct_flx);
-        } else
+        if (ctx->cfg.ct == 2)
+            hipLaunchKernelGGL((ct_emf_upwind_kernel<T, CT_EMF_TY>), dim3(ug.nblocks), dim3(TX * CT_EMF_TY), 0,
+                               ctx->stream, c, ug);
+        else
             hipLaunchKernelGGL(ct_emf_kernel<T>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, c);
         HIP_TRY(ctx, hipGetLastError());
         hipLaunchKernelGGL((ct_face_kernel<T, KIND, last_stage(KIND)>), dim3(nb), dim3(RED_THREADS), 0,
@@ -716,7 +722,7 @@ mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out)
     hipError_t e = hipMalloc(&ctx->u1_scratch, (size_t)ctx->ns * ctx->ncell * ctx->elem);
     if (e == hipSuccess && cfg->time_order == 3)
         e = hipMalloc(&ctx->u2_scratch, (size_t)ctx->ns * ctx->ncell * ctx->elem);
-    if (e == hipSuccess && cfg->ct) e = hipMalloc(&ctx->ct_flx, (size_t)6 * ctx->ncell * ctx->elem);
+    if (e == hipSuccess && cfg->ct == 1) e = hipMalloc(&ctx->ct_flx, (size_t)6 * ctx->ncell * ctx->elem);
     if (e == hipSuccess && cfg->ct) e = hipMalloc(&ctx->ct_emf, (size_t)3 * ctx->ncell * ctx->elem);
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->part, (size_t)NPART * ctx->part_cap * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->result, NPART * sizeof(double));
