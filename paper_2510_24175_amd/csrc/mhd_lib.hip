@@ -55,7 +55,7 @@ namespace {
 constexpr int CFL_MAX_BLOCKS = 4096;
 // rows of an upwind EMF tile (TX x 8 columns: 124 KB of LDS in FP64, one
 // workgroup of 8 waves per compute unit; 62 KB in FP32, two)
-constexpr int CT_EMF_TY = 8;
+template <typename T> constexpr int ct_emf_rows() { return 8; }
 
 mhd_status fail(mhd_ctx *ctx, mhd_status st, const char *msg)
 {
@@ -268,7 +268,7 @@ mhd_status launch_step_ct(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt,
     // pass has eight workgroups per compute unit
     CTTiles ug;
     ug.tiles_x = (a.nx + TX - 1) / TX;
-    ug.tiles_y = (a.ny + CT_EMF_TY - 1) / CT_EMF_TY;
+    ug.tiles_y = (a.ny + ct_emf_rows<T>() - 1) / ct_emf_rows<T>();
     ug.kz = 32;
     while (ug.kz > 4 && (long long)ug.tiles_x * ug.tiles_y * ((a.nz + ug.kz - 1) / ug.kz) < 8 * 256) ug.kz >>= 1;
     ug.nblocks = ug.tiles_x * ug.tiles_y * ((a.nz + ug.kz - 1) / ug.kz);
@@ -288,7 +288,7 @@ mhd_status launch_step_ct(mhd_ctx *ctx, const T *un, T *unext, T *u1, double dt,
         c.uin = uin;
         c.uout = uout;
         if (ctx->cfg.ct == 2)
-            hipLaunchKernelGGL((ct_emf_upwind_kernel<T, CT_EMF_TY>), dim3(ug.nblocks), dim3(TX * CT_EMF_TY), 0,
+            hipLaunchKernelGGL((ct_emf_upwind_kernel<T, ct_emf_rows<T>()>), dim3(ug.nblocks), dim3(TX * ct_emf_rows<T>()), 0,
                                ctx->stream, c, ug);
         else
             hipLaunchKernelGGL(ct_emf_kernel<T>, dim3(nb), dim3(RED_THREADS), 0, ctx->stream, c);
