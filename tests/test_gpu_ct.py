@@ -81,6 +81,19 @@ def test_cpa_3d_ct(torch_cuda, dtype, riemann, emf):
 
 @pytest.mark.parametrize("emf", EMFS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [(5, 3, 2), (2, 7, 3), (66, 2, 9), (3, 4, 33)], ids=lambda n: "x".join(map(str, n)))
+def test_ct_thin_grids(torch_cuda, dtype, n, emf):
+    # axes of 2 or 3 cells, whose stencil halos wrap around the grid more
+    # than once (the EMF tiles take their periodic images by index
+    # arithmetic), and a z axis of several short chunks with a partial one
+    s, V = W.orszag_tang_3d_ct(n, emf=emf)
+    _check(torch_cuda, f"orszag_tang_3d_ct thin {emf}", s, V, dtype, 8)
+    s, V = W.cpa_wave_3d_ct(n, emf=emf)
+    _check(torch_cuda, f"cpa_3d_ct thin {emf}", s, V, dtype, 8)
+
+
+@pytest.mark.parametrize("emf", EMFS)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_ct_sums_and_cfl(torch_cuda, dtype, emf):
     # the reductions of the last face update against the oracle's
     torch = torch_cuda
