@@ -54,7 +54,8 @@
  * Ownership: the caller owns every state, adjoint and primitive buffer.
  * The library owns the context and its scratch (stage-1 buffer when the
  * caller passes none, the SSP-RK3 stage-2 buffer, the constrained-transport
- * flux and EMF buffers, reduction partials, result and error words), all
+ * EMF buffer and, with the mean EMF, face-flux buffer, reduction partials,
+ * result and error words), all
  * allocated by mhd_init and freed by mhd_destroy; mhd_step,
  * mhd_step_adjoint and mhd_cfl_dt allocate nothing.
  *
@@ -131,7 +132,8 @@ typedef struct {
  * solver, limiter, time_order, ct not 0, 1 or 2, ct with glm = 1, mixed
  * periodic/outflow on one axis, gamma <= 1, cfl not in (0,1],
  * glm_alpha < 0), MHD_ERR_UNSUPPORTED for MHD_FLAG_ADJOINT with WENO-Z,
- * SSP-RK3 or ct = 1 and for ct = 1 on a grid that is not 3D and periodic,
+ * SSP-RK3 or ct = 1 or 2 and for ct = 1 or 2 on a grid that is not 3D and
+ * periodic,
  * MHD_ERR_NO_DEVICE when no gfx950 device is current, MHD_ERR_HIP when an
  * allocation fails.  *out is NULL on failure. */
 mhd_status mhd_init(const mhd_config *cfg, void *hip_stream, mhd_ctx **out);
