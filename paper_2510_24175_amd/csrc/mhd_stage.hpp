@@ -100,8 +100,10 @@ __device__ __forceinline__ bool cell_speeds(const T *u, double gamma, const doub
 // FP32 signal speeds of one FP32 cell state, used only to pick the cell
 // whose FP64 speeds a thread reports: ls = max_d (|v_d| + c_f,d)/dx_d,
 // lc = max_d (|v_d| + c_f,d).  The discriminant is formed from the
-// transverse field, (a^2 - b^2)^2 + 4 a^2 b_t^2, a sum of non-negative terms,
-// so the estimate carries only rounding of the order of ten FP32 ulps.
+// transverse field, (a^2 - b^2)^2 + 4 a^2 b_t^2, a sum of non-negative terms;
+// the estimate carries rounding of the order of ten FP32 ulps plus the FP32
+// pressure's cancellation, which reaches |v| + c_f only through the sound
+// speed (about gamma M / 4 ulps at Mach M).
 // Returns false for rho <= 0, p <= 0 or non-finite values.
 template <int NDIM>
 __device__ __forceinline__ bool cell_speeds_f32(const float *u, float gamma, const float *idx, float &ls,
