@@ -258,14 +258,15 @@ stage_kernel(const StageArgs<T> a)
     const int tx = t & (TX - 1);
     const int ty = t / TX;  // tile row of a column owner (>= TY: helper)
     const int wave = __builtin_amdgcn_readfirstlane(ty);
-    // With one wave per tile row every wave owns its row.  For 3D FP32 PLM
-    // the owner test is folded at compile time: the compiler then holds the
-    // stages to 127 and 165 registers (four and three workgroups per compute
-    // unit) instead of 138 and 168 with 8 spilled.  Elsewhere it is left to
-    // run time, which its allocation favours (FP64 PLM: 0 and 24 spilled
-    // registers against 28 and 87; 2D FP32 PLM: 127 against 129, a
-    // workgroup per compute unit more).
-    constexpr bool ALL_OWN = stage_row_waves<T, LIM>() == 1 && sizeof(T) == 4 && !WENO && NDIM == 3;
+    // With one wave per tile row every wave owns its row.  For the 3D FP32
+    // kernels the owner test is folded at compile time: the compiler then
+    // holds the PLM stages to 127 and 165 registers (four and three
+    // workgroups per compute unit) instead of 138 and 168 with 8 spilled, and
+    // the WENO-Z stages (one workgroup per unit either way) run 1-4% faster.
+    // Elsewhere it is left to run time, which the compiler's allocation
+    // favours (FP64 PLM: 0 and 24 spilled registers against 28 and 87; 2D
+    // FP32 PLM: 127 against 129, a workgroup per compute unit more).
+    constexpr bool ALL_OWN = stage_row_waves<T, LIM>() == 1 && sizeof(T) == 4 && NDIM == 3;
     const bool owner = ALL_OWN || wave < TY;  // wave-uniform
     const int lb = logical_block(blockIdx.x, a.nblocks);
     const int tile_x = lb % a.tiles_x;
