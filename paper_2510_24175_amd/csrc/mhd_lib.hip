@@ -79,7 +79,9 @@ mhd_status fail_hip(mhd_ctx *ctx, const char *what, hipError_t e)
 // stage_row_waves).  FP32 PLM: 4 rows, three
 // workgroups (12 waves) per compute unit at the 168-VGPR budget; measured
 // faster than 6 rows (two workgroups of 6 waves) by a third and than 8 rows
-// (one workgroup of 8 waves) by 13%.  FP32 WENO-Z: 8 rows, one workgroup of
+// (one workgroup of 8 waves) by 13%; an 8-row first stage at two workgroups
+// of 8 waves (125 registers, a tenth fewer face items and half the halo
+// conversions per cell) measured 2% slower.  FP32 WENO-Z: 8 rows, one workgroup of
 // 8 waves and 155 KB of LDS per compute unit; the three-cell y halo costs
 // half as much per cell as with 4 rows (measured 9% faster).  FP64 (register
 // bound, WENO-Z at 140 KB of LDS): 4 rows.  1D: 1 row.
