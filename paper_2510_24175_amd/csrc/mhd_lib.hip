@@ -81,7 +81,9 @@ mhd_status fail_hip(mhd_ctx *ctx, const char *what, hipError_t e)
 // faster than 6 rows (two workgroups of 6 waves) by a third and than 8 rows
 // (one workgroup of 8 waves) by 13%; an 8-row first stage at two workgroups
 // of 8 waves (125 registers, a tenth fewer face items and half the halo
-// conversions per cell) measured 2% slower.  FP32 WENO-Z: 8 rows, one workgroup of
+// conversions per cell) measured 2% slower, and a 6-row last stage at two
+// workgroups of 6 waves (the same 12 waves per compute unit; 6 waves do not
+// spread evenly over its 4 SIMDs) 60% slower.  FP32 WENO-Z: 8 rows, one workgroup of
 // 8 waves and 155 KB of LDS per compute unit; the three-cell y halo costs
 // half as much per cell as with 4 rows (measured 9% faster).  FP64 (register
 // bound, WENO-Z at 140 KB of LDS): 4 rows.  1D: 1 row.
