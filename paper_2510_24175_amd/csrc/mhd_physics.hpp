@@ -133,8 +133,11 @@ template <int LIM, typename T> __device__ __forceinline__ T limited_slope(T a, T
 //
 // FP64: the weights are multiplied through by (beta0+eps)(beta1+eps)(beta2+eps),
 // W_k = prod_{j != k}(beta_j + eps) (beta_k + eps + tau5), and both faces are
-// normalised with one division (the products stay within FP64 range for
-// indicators between eps and 1e60).  FP32: the reciprocals are the hardware
+// normalised with one reciprocal of the product of the two weight sums, the
+// Newton-refined one (within an ulp).  That product lies between eps^6 and
+// about 4 beta_max^6, so it and its reciprocal stay normal for indicators
+// between eps and 1e51 (differences of a few 1e25 between neighbouring cell
+// values).  FP32: the reciprocals are the hardware
 // approximation and the ratio tau5/(beta_k + eps) is capped at 1e18 so that
 // the weights stay finite for jumps whose indicators exceed FLT_MAX * eps; the
 // cap only binds where two candidates are both 1e18 times smoother than
@@ -176,7 +179,7 @@ __device__ __forceinline__ void wenoz_pair(T v0, T v1, T v2, T v3, T v4, T &rgt,
     const T nr = a0r * d0r + a1 * d1r + a2r * d2r, sr = a0r + a1 + a2r;
     const T nl = a0l * d0l + a1 * d1l + a2l * d2l, sl = a0l + a1 + a2l;
     if constexpr (sizeof(T) == 8) {
-        const T inv = T(1) / (sr * sl);
+        const T inv = Num<T>::rcp(sr * sl);
         rgt = v2 + nr * (sl * inv);
         lft = v2 + nl * (sr * inv);
     } else {
