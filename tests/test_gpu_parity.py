@@ -152,6 +152,44 @@ def test_uniform_state_bitwise(torch_cuda, dtype, ndim):
     assert torch.equal(U, U0)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("scheme", ["plm-hlld", "plm-hll", "wenoz-hlld-rk3"])
+def test_field_aligned_degenerate_uniform(torch_cuda, dtype, scheme):
+    # rho = 1, v = (1/2, -1/4, 1/8), p = 1/2, B = (1, 0, 0), gamma = 2: the
+    # primitive <-> conserved conversions are exact in either precision and
+    # a^2 = b^2 = b_x^2 = 1, so along x the fast-speed discriminant is exactly
+    # 0 (c_f = 1, the square root of zero) and so is the HLLD star
+    # denominator D = rho (S - u)(S - S_M) - B_n^2 of every x face (the
+    # degenerate branch); along y and z c_f = sqrt(2).  The CFL maxima have a
+    # closed form, and the fluxes cancel, so the state stays put (to an ulp
+    # per step with the SSP-RK3 combinations).
+    import math
+    torch = torch_cuda
+    from paper_2510_24175_amd.mhd import Context
+    from paper_2510_24175_amd.rollout import advance
+    lim, riemann, order = {"plm-hlld": ("minmod", "hlld", 2), "plm-hll": ("minmod", "hll", 2),
+                           "wenoz-hlld-rk3": ("wenoz", "hlld", 3)}[scheme]
+    s, V = W.uniform((70, 9, 7), ndim=3, state=(1.0, 0.5, -0.25, 0.125, 0.5, 1.0, 0.0, 0.0, 0.0),
+                     riemann=riemann, gamma=2.0)
+    s["limiter"], s["time_order"] = lim, order
+    _say(f"[gpu-parity] field-aligned degenerate uniform {scheme} dtype={dtype}")
+    ctx = Context(s, dtype)
+    U0 = ctx.prim_to_cons(torch.from_numpy(V).cuda())
+    lam = [0.5 + 1.0, 0.25 + math.sqrt(2.0), 0.125 + math.sqrt(2.0)]
+    dx = [(s["hi"][d] - s["lo"][d]) / s["n"][d] for d in range(3)]
+    dt_ref = s["cfl"] / max(l / h for l, h in zip(lam, dx))
+    ch_ref = max(lam)
+    dt, ch = ctx.cfl_dt(U0)
+    assert abs(dt / dt_ref - 1) <= 2e-15 and abs(ch / ch_ref - 1) <= 2e-15, (dt, dt_ref, ch, ch_ref)
+    U, _, hist = advance(ctx, U0, nsteps=20)
+    if order == 2:
+        assert torch.equal(U, U0)
+        assert all(h[0] == dt and h[1] == ch for h in hist)
+    else:
+        rtol = 1e-14 if dtype == "f64" else 1e-5
+        assert torch.allclose(U, U0, rtol=rtol, atol=0.0)
+
+
 def test_run_to_run_bitwise(torch_cuda):
     torch = torch_cuda
     s, V = W.turbulence((40, 40, 40))

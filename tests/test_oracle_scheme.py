@@ -270,6 +270,25 @@ def test_cfl_closed_form_uniform():
     assert dt == pytest.approx(0.3 / max(l / h for l, h in zip(lam, dx)), rel=1e-14)
 
 
+@pytest.mark.parametrize("riemann", ["hll", "hlld"])
+def test_field_aligned_degenerate_uniform(riemann):
+    # a^2 = b^2 = b_x^2 = 1 exactly (rho 1, p 1/2, gamma 2, B along x, dyadic
+    # velocities): the x fast speed is 1 from a zero discriminant and every
+    # HLLD x face takes the degenerate star branch (D = 0); the CFL maxima
+    # are (|v_d| + c_f,d) with c_f = (1, sqrt 2, sqrt 2), and the state is a
+    # fixed point of the step
+    state = (1.0, 0.5, -0.25, 0.125, 0.5, 1.0, 0.0, 0.0, 0.0)
+    s, V = W.uniform((8, 6, 4), ndim=3, state=state, riemann=riemann, gamma=2.0)
+    o = C.Oracle(s)
+    U0 = o.prim_to_cons(V)
+    dt, ch = o.cfl(U0)
+    lam = [1.5, 0.25 + math.sqrt(2.0), 0.125 + math.sqrt(2.0)]
+    assert ch == pytest.approx(max(lam), rel=1e-15)
+    assert dt == pytest.approx(0.3 / max(l * n for l, n in zip(lam, (8, 6, 4))), rel=1e-15)
+    U1 = o.step(U0, dt, ch)
+    assert np.array_equal(U1, U0)
+
+
 def test_nonphysical_state_is_an_error():
     s, V = W.uniform((6, 6, 6), ndim=3)
     o = C.Oracle(s)
