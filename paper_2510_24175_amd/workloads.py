@@ -190,6 +190,35 @@ def cpa_wave_3d(n, amplitude=0.1, riemann="hlld", cfl=0.3, limiter="wenoz", time
     return s, V
 
 
+# -------------------------------------------- largest grids (on device) ----
+
+def smooth_modes_device(n, device, riemann="hlld", cfl=0.3, limiter="minmod", time_order=2):
+    """Smooth periodic fields on an n^3 grid, built with torch on `device`
+    (for grids whose FP64 primitives do not fit comfortably in host memory):
+    a few low Fourier modes with a different wave vector in every component,
+    so that a permuted or shifted axis shows in any cell, and a
+    divergence-free field (each B component independent of its own
+    coordinate).  Returns (setup, V) with V a float64 (9, n, n, n) tensor.
+    Deterministic; no random numbers."""
+    import torch
+    s = make_setup("smooth_modes", 3, (n, n, n), gamma=5.0 / 3.0, cfl=cfl, riemann=riemann,
+                   limiter=limiter, time_order=time_order)
+    c = (torch.arange(n, dtype=torch.float64, device=device) + 0.5) / n
+    x, y, z = c.view(1, 1, n), c.view(1, n, 1), c.view(n, 1, 1)
+    tp = 2.0 * math.pi
+    V = torch.empty((9, n, n, n), dtype=torch.float64, device=device)
+    V[0] = 1.0 + 0.25 * torch.sin(tp * (x + 2.0 * y + 3.0 * z) + 0.3)
+    V[1] = 0.4 * torch.sin(tp * (y + z))
+    V[2] = 0.4 * torch.sin(tp * (z + 2.0 * x) + 0.7)
+    V[3] = 0.4 * torch.sin(tp * (x - y) + 1.1)
+    V[4] = 1.0 + 0.2 * torch.cos(tp * (3.0 * x - y + z))
+    V[5] = 0.3 * torch.cos(tp * (y - 2.0 * z))
+    V[6] = 0.3 * torch.cos(tp * (z + x) + 0.5)
+    V[7] = 0.3 * torch.cos(tp * (2.0 * x - y) + 0.9)
+    V[8] = 0.0
+    return s, V
+
+
 # -------------------------------------------------------- turbulence -------
 
 def half_space_modes(kmax=4):

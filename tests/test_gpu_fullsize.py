@@ -23,6 +23,11 @@ benchmark uses.
 * 1024^2 Orszag-Tang: 10 FP32 steps against the oracle on the full grid;
   the run to t = 0.5 in FP64 and FP32 checked for conservation and for the
   180-degree rotation symmetry of the setup.
+* 1024^3 FP32 (1.07G cells, near the memory limit of one device; a state
+  holds 9.7G elements, past 2^32): one PLM/SSP-RK2 and one WENO-Z/SSP-RK3
+  step at sampled cells against the oracle on windows of the same input,
+  FP64 conservation over two steps, the fused CFL of the step against the
+  standalone one.
 """
 import numpy as np
 import pytest
@@ -331,3 +336,65 @@ def test_orszag_tang_1024():
         assert abs(t - t_long) < 1e-12
         assert asym <= sym_tol
         assert dcons <= cons_tol
+
+
+def _sample_cells_max(n, rng, count=40):
+    """(k, j, i) cells: corners, x-tile, y-tile (4 and 8 rows) and z-chunk
+    boundaries, the last planes (largest linear indices), random."""
+    cells = [(0, 0, 0), (n - 1, n - 1, n - 1), (63, 3, 63), (64, 4, 64), (n - 64, 7, 63),
+             (n - 65, 8, 64), (n - 1, 0, n - 1), (0, n - 1, n - 2), (n // 2, n // 2 - 1, 511),
+             (n - 2, n - 3, n - 1), (n - 1, n - 1, 0), (1, n - 1, n - 1)]
+    while len(cells) < count:
+        cells.append(tuple(int(v) for v in rng.integers(0, n, 3)))
+    return cells
+
+
+@pytest.mark.parametrize("scheme", ["plm-rk2", "wenoz-rk3"])
+def test_largest_grid_1024_cubed_sampled(scheme):
+    from paper_2510_24175_amd.mhd import Context
+    n = 1024
+    lim, order = {"plm-rk2": ("minmod", 2), "wenoz-rk3": ("wenoz", 3)}[scheme]
+    # dependency radius of one step: 2 (PLM) or 3 (WENO-Z) cells per stage
+    r = 5 if order == 2 else 10
+    _say(f"[gpu-fullsize] {n}^3 FP32 {scheme}: fields on the device")
+    s, V = W.smooth_modes_device(n, "cuda", limiter=lim, time_order=order)
+    ow = C.Oracle(_window_setup(s, r, n) | {"limiter": lim, "time_order": order})
+    # a fixed step below the CFL limit (max |v| + c_f < 2.5 for these fields)
+    dt, ch = 1.0e-4, 2.5
+    dmp = ow.damp(dt, ch)
+    ctx = Context(s, "f32")
+    U = ctx.prim_to_cons(V)
+    cells = _sample_cells_max(n, np.random.default_rng(21))
+    wins = []
+    for (k, j, i) in cells:
+        ix = [torch.tensor([(c + a) % n for a in range(-r, r + 1)], device="cuda") for c in (k, j, i)]
+        wins.append(V.index_select(1, ix[0]).index_select(2, ix[1]).index_select(3, ix[2]).cpu().numpy())
+    del V
+    torch.cuda.empty_cache()
+    cs = np.maximum(np.array([float(U[q].abs().max()) for q in range(9)]), 1e-2)
+    dtg, chg = ctx.cfl_dt(U)
+    _say(f"    standalone CFL dt={dtg:.4e} c_h={chg:.4e}")
+    assert np.isfinite(dtg) and dt <= dtg and 0 < chg < ch
+    out = torch.empty_like(U)
+    _say("    step 1")
+    ctx.step(U, out, dt, ch, dmp)
+    dt1, ch1, sums1 = ctx.step_info()
+    assert (dt1, ch1) == ctx.cfl_dt(out)
+    _say("    step 2")
+    ctx.step(out, U, dt, ch, dmp)
+    _, _, sums2 = ctx.step_info()
+    scale = np.array([float(out[q].abs().sum(dtype=torch.float64)) for q in range(9)]) * ow.cell_volume
+    dsum = np.abs(np.array(sums2) - np.array(sums1))[:8] / scale[:8]
+    _say(f"    conservation over one step (FP64 sums): {dsum.max():.2e}")
+    assert dsum.max() <= 1e-6
+    worst = 0.0
+    for (k, j, i), w in zip(cells, wins):
+        ref = ow.step(ow.prim_to_cons(w), dt, ch, dmp)[:, r, r, r]
+        got = out[:, k, j, i].double().cpu().numpy()
+        err = (np.abs(got - ref) / cs).max()
+        worst = max(worst, err)
+        assert err <= 1e-5, ((k, j, i), got, ref)
+    _say(f"    worst sampled-cell error (per-component scaled): {worst:.2e}")
+    ctx.close()
+    del out, U
+    torch.cuda.empty_cache()
