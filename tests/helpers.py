@@ -74,3 +74,16 @@ def have_gpu():
 
 
 requires_gpu = pytest.mark.skipif(not have_gpu(), reason="needs a GPU")
+
+
+def face_divergence(U, dx):
+    """Discrete divergence of the face field of a constrained-transport state
+    U[12][nz][ny][nx] (components 9..11: the field on each cell's lower x, y
+    and z faces) on a periodic grid: sum over axes of (upper face - lower
+    face) / dx_d, per cell."""
+    U = np.asarray(U, dtype=np.float64)
+    div = np.zeros(U.shape[1:])
+    for d, ax in ((0, 2), (1, 1), (2, 0)):
+        b = U[9 + d]
+        div += (np.roll(b, -1, axis=ax) - b) / dx[d]
+    return div

@@ -66,17 +66,21 @@ def test_step_adjoint_matches_reference(name, setup, V, dtype):
     from paper_2510_24175_amd.mhd import Context
     _say(f"[gpu-adjoint] step {name} {dtype}")
     o = C.Oracle(setup)
-    dt, ch = o.cfl(o.prim_to_cons(V))
+    Uo = o.prim_to_cons(V)
+    dt, ch = o.cfl(Uo)
     dmp = o.damp(dt, ch)
     ctx = Context(setup, dtype, adjoint=True)
-    Ug = ctx.prim_to_cons(torch.from_numpy(V).cuda())
+    # both sides start from the oracle's conserved state, rounded to the
+    # state type on the host for FP32
+    Us = Uo if dtype == "f64" else Uo.astype(np.float32)
+    Ug = torch.from_numpy(Us).cuda()
     lamp = np.random.default_rng(5).normal(size=Ug.shape)
     lamn = torch.empty(Ug.shape, dtype=torch.float64, device="cuda")
     ctx.step_adjoint(Ug, None, torch.from_numpy(lamp).cuda(), lamn, dt, ch, dmp)
     torch.cuda.synchronize()
     g_gpu = lamn.cpu().numpy()
-    # reference gradient at the same (state-type rounded) state
-    Ut = torch.from_numpy(Ug.double().cpu().numpy()).requires_grad_(True)
+    # reference gradient at that same state
+    Ut = torch.from_numpy(Us.astype(np.float64)).requires_grad_(True)
     J = (torch.from_numpy(lamp) * R.step(Ut, setup, dt, ch, dmp)).sum()
     (g_ref,) = torch.autograd.grad(J, Ut)
     g_ref = g_ref.numpy()

@@ -188,12 +188,15 @@ def test_adjoint_512_fp64_sampled_against_reference(turb512):
     s, V, o, _, _, _, _ = turb512
     n = N512
     _say("[gpu-fullsize] adjoint 512^3 f64: sampled cells")
+    # the oracle's conserved state of the generic fields, its CFL step and
+    # decay factor feed both the GPU adjoint and the reference
+    Vh = _generic512(V).cpu().numpy()
+    Uo = o.prim_to_cons(Vh)
+    del Vh
+    dt, ch = o.cfl(Uo)
+    dmp = o.damp(dt, ch)
     ctx = Context(s, "f64", adjoint=True)
-    Vg = _generic512(V)
-    Ug = ctx.prim_to_cons(Vg)
-    del Vg
-    dt, ch = ctx.cfl_dt(Ug)
-    dmp = ctx.damp(dt, ch)
+    Ug = torch.from_numpy(Uo).cuda()
     gen = torch.Generator(device="cuda").manual_seed(21)
     lam = torch.randn(Ug.shape, dtype=torch.float64, device="cuda", generator=gen)
     lamn = torch.empty_like(lam)
@@ -205,7 +208,7 @@ def test_adjoint_512_fp64_sampled_against_reference(turb512):
     got, ref = [], []
     for (k, j, i) in _sample_cells(n, rng, count=16):
         kk, jj, ii = (torch.tensor([(c + a) % n for a in range(-r, r + 1)], device="cuda") for c in (k, j, i))
-        Uw = Ug[:, kk][:, :, jj][:, :, :, ii].cpu()
+        Uw = torch.from_numpy(_window(Uo, k, j, i, r, n))
         lw = lam[:, kk][:, :, jj][:, :, :, ii].cpu()
         Ut = Uw.clone().requires_grad_(True)
         J = (lw * R.step(Ut, ws, dt, ch, dmp)).sum()
@@ -217,7 +220,7 @@ def test_adjoint_512_fp64_sampled_against_reference(turb512):
     _say(f"    worst sampled-cell error (per-component scaled): {err:.2e}")
     assert err <= 1e-10, err
     ctx.close()
-    del Ug, lam, lamn
+    del Ug, lam, lamn, Uo
     torch.cuda.empty_cache()
 
 
