@@ -192,21 +192,31 @@ def cpa_wave_3d(n, amplitude=0.1, riemann="hlld", cfl=0.3, limiter="wenoz", time
 
 # -------------------------------------------- largest grids (on device) ----
 
-def smooth_modes_device(n, device, riemann="hlld", cfl=0.3, limiter="minmod", time_order=2):
-    """Smooth periodic fields on an n^3 grid, built with torch on `device`
-    (for grids whose FP64 primitives do not fit comfortably in host memory):
-    a few low Fourier modes with a different wave vector in every component,
-    so that a permuted or shifted axis shows in any cell, and a
-    divergence-free field (each B component independent of its own
-    coordinate).  Returns (setup, V) with V a float64 (9, n, n, n) tensor.
-    Deterministic; no random numbers."""
+def smooth_modes_device(n, device, riemann="hlld", cfl=0.3, limiter="minmod", time_order=2,
+                        ct_emf=None):
+    """Smooth periodic fields on an n^3 (or n = (nx, ny, nz)) grid on the unit
+    box, built with torch on `device` (for grids whose FP64 primitives do not
+    fit comfortably in host memory): a few low Fourier modes with a different
+    wave vector in every component, so that a permuted or shifted axis shows
+    in any cell, and a divergence-free field (each B component independent of
+    its own coordinate).  With ct_emf ("mean" or "upwind") the setup is for
+    constrained transport (GLM off) and the face fields, components 9..11,
+    equal the cell field (each is constant along its own axis, so the
+    discrete divergence is exactly zero).  Returns (setup, V) with V a float64
+    (9 or 12, nz, ny, nx) tensor.  Deterministic; no random numbers."""
     import torch
-    s = make_setup("smooth_modes", 3, (n, n, n), gamma=5.0 / 3.0, cfl=cfl, riemann=riemann,
+    nx, ny, nz = (n, n, n) if isinstance(n, int) else tuple(n)
+    s = make_setup("smooth_modes", 3, (nx, ny, nz), gamma=5.0 / 3.0, cfl=cfl, riemann=riemann,
                    limiter=limiter, time_order=time_order)
-    c = (torch.arange(n, dtype=torch.float64, device=device) + 0.5) / n
-    x, y, z = c.view(1, 1, n), c.view(1, n, 1), c.view(n, 1, 1)
+    if ct_emf is not None:
+        s["ct"], s["glm"], s["ct_emf"] = True, False, ct_emf
+
+    def centres(m):
+        return (torch.arange(m, dtype=torch.float64, device=device) + 0.5) / m
+
+    x, y, z = centres(nx).view(1, 1, nx), centres(ny).view(1, ny, 1), centres(nz).view(nz, 1, 1)
     tp = 2.0 * math.pi
-    V = torch.empty((9, n, n, n), dtype=torch.float64, device=device)
+    V = torch.empty((9 if ct_emf is None else 12, nz, ny, nx), dtype=torch.float64, device=device)
     V[0] = 1.0 + 0.25 * torch.sin(tp * (x + 2.0 * y + 3.0 * z) + 0.3)
     V[1] = 0.4 * torch.sin(tp * (y + z))
     V[2] = 0.4 * torch.sin(tp * (z + 2.0 * x) + 0.7)
@@ -216,6 +226,8 @@ def smooth_modes_device(n, device, riemann="hlld", cfl=0.3, limiter="minmod", ti
     V[6] = 0.3 * torch.cos(tp * (z + x) + 0.5)
     V[7] = 0.3 * torch.cos(tp * (2.0 * x - y) + 0.9)
     V[8] = 0.0
+    if ct_emf is not None:
+        V[9:12] = V[5:8]
     return s, V
 
 
