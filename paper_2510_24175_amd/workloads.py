@@ -193,7 +193,7 @@ def cpa_wave_3d(n, amplitude=0.1, riemann="hlld", cfl=0.3, limiter="wenoz", time
 # -------------------------------------------- largest grids (on device) ----
 
 def smooth_modes_device(n, device, riemann="hlld", cfl=0.3, limiter="minmod", time_order=2,
-                        ct_emf=None):
+                        ct_emf=None, ripple=0.0):
     """Smooth periodic fields on an n^3 (or n = (nx, ny, nz)) grid on the unit
     box, built with torch on `device` (for grids whose FP64 primitives do not
     fit comfortably in host memory): a few low Fourier modes with a different
@@ -202,8 +202,11 @@ def smooth_modes_device(n, device, riemann="hlld", cfl=0.3, limiter="minmod", ti
     its own coordinate).  With ct_emf ("mean" or "upwind") the setup is for
     constrained transport (GLM off) and the face fields, components 9..11,
     equal the cell field (each is constant along its own axis, so the
-    discrete divergence is exactly zero).  Returns (setup, V) with V a float64
-    (9 or 12, nz, ny, nx) tensor.  Deterministic; no random numbers."""
+    discrete divergence is exactly zero).  ripple > 0 (GLM only) adds
+    ripple * sin(2 pi (x + 2y + 3z) + q) to component q, so that no component
+    is constant along any axis (limiter arguments then never tie at rounding
+    noise).  Returns (setup, V) with V a float64 (9 or 12, nz, ny, nx) tensor.
+    Deterministic; no random numbers."""
     import torch
     nx, ny, nz = (n, n, n) if isinstance(n, int) else tuple(n)
     s = make_setup("smooth_modes", 3, (nx, ny, nz), gamma=5.0 / 3.0, cfl=cfl, riemann=riemann,
@@ -226,6 +229,11 @@ def smooth_modes_device(n, device, riemann="hlld", cfl=0.3, limiter="minmod", ti
     V[6] = 0.3 * torch.cos(tp * (z + x) + 0.5)
     V[7] = 0.3 * torch.cos(tp * (2.0 * x - y) + 0.9)
     V[8] = 0.0
+    if ripple:
+        if ct_emf is not None:
+            raise ValueError("ripple breaks the divergence-free face field")
+        for q in range(9):
+            V[q] += ripple * torch.sin(tp * (x + 2.0 * y + 3.0 * z) + float(q))
     if ct_emf is not None:
         V[9:12] = V[5:8]
     return s, V

@@ -30,7 +30,9 @@ benchmark uses.
   standalone one; constrained transport (WENO-Z/SSP-RK3, both edge EMFs)
   at 1024 x 1024 x 640 FP32 (a 12-component state holds 8.05G elements):
   sampled cells against the oracle on periodic windows, face divergence
-  and conservation.
+  and conservation; the FP64 adjoint step at 1024 x 1024 x 464 (each FP64
+  lambda array 4.38G elements) at sampled cells against the FP64 PyTorch
+  reference gradient on windows of the oracle's state.
 """
 import numpy as np
 import pytest
@@ -471,4 +473,59 @@ def test_largest_grid_ct_sampled(emf):
     _say(f"    worst sampled-cell error (per-component scaled): {worst:.2e}")
     ctx.close()
     del out, U
+    torch.cuda.empty_cache()
+
+
+def test_largest_grid_adjoint_fp64_sampled():
+    """lambda_n of one FP64 adjoint step (stage 1 recomputed) at sampled
+    cells against the FP64 PyTorch reference gradient on 19^3 outflow
+    windows; the oracle's conserved state of the rippled smooth fields (no
+    component constant along an axis) is the input of both."""
+    from paper_2510_24175_amd.mhd import Context
+    shape = (1024, 1024, 464)
+    nx, ny, nz = shape
+    r = 9
+    _say(f"[gpu-fullsize] adjoint {nx}x{ny}x{nz} f64: fields, oracle state")
+    s, V = W.smooth_modes_device(shape, "cuda", ripple=0.05)
+    Vh = V.cpu().numpy()
+    del V
+    torch.cuda.empty_cache()
+    o = C.Oracle(s)
+    Uo = o.prim_to_cons(Vh)
+    del Vh
+    dt, ch = 1.0e-4, 2.5
+    dmp = o.damp(dt, ch)
+    ws = W.make_setup("window", 3, (2 * r + 1,) * 3, gamma=s["gamma"], cfl=s["cfl"],
+                      riemann=s["riemann"], bc=(("outflow", "outflow"),) * 3,
+                      hi=tuple((2 * r + 1) / m for m in shape))
+    ctx = Context(s, "f64", adjoint=True)
+    Ug = torch.from_numpy(Uo).cuda()
+    gen = torch.Generator(device="cuda").manual_seed(22)
+    lam = torch.randn(Ug.shape, dtype=torch.float64, device="cuda", generator=gen)
+    lamn = torch.empty_like(lam)
+    _say("    adjoint step")
+    ctx.step_adjoint(Ug, None, lam, lamn, dt, ch, dmp)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(24)
+    cells = [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz - 1, 3, 64), (nz - 2, ny - 5, 0), (63, 7, 63),
+             (64, 8, 1023)]
+    while len(cells) < 14:
+        cells.append((int(rng.integers(0, nz)), int(rng.integers(0, ny)), int(rng.integers(0, nx))))
+    got, ref = [], []
+    for (k, j, i) in cells:
+        ax = [[(c + a) % m for a in range(-r, r + 1)] for c, m in ((k, nz), (j, ny), (i, nx))]
+        Uw = torch.from_numpy(Uo[np.ix_(range(9), *ax)])
+        kk, jj, ii = (torch.tensor(v, device="cuda") for v in ax)
+        lw = lam.index_select(1, kk).index_select(2, jj).index_select(3, ii).cpu()
+        Ut = Uw.clone().requires_grad_(True)
+        J = (lw * R.step(Ut, ws, dt, ch, dmp)).sum()
+        (g,) = torch.autograd.grad(J, Ut)
+        ref.append(g[:, r, r, r].numpy())
+        got.append(lamn[:, k, j, i].cpu().numpy())
+    got, ref = np.array(got), np.array(ref)
+    err = (np.abs(got - ref) / np.abs(ref).max(axis=0)).max()
+    _say(f"    worst sampled-cell error (per-component scaled): {err:.2e}")
+    assert err <= 1e-10, err
+    ctx.close()
+    del Ug, lam, lamn, Uo
     torch.cuda.empty_cache()
