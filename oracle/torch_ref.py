@@ -18,7 +18,6 @@ cannot poison gradients.
 
 Arrays: (9, nz, ny, nx) float64 tensors on the CPU.
 """
-import math
 
 import numpy as np
 import torch

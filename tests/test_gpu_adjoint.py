@@ -12,7 +12,6 @@
 * the same gradient against the reference gradient of the PyTorch step at
   32^3 (the workload's 200 steps, checkpoints every 20).
 """
-import sys
 
 import numpy as np
 import pytest

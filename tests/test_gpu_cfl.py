@@ -6,7 +6,6 @@ the estimate's error; on these workloads (ragged 3D turbulence and 256^3 in
 the benchmark's launch shape, WENO-Z + SSP-RK3, 2D and 1D, a uniform state
 whose every cell ties) every step's dt and c_h are those of the all-FP64
 reduction bit for bit.  FP64 states take every cell's FP64 speeds in both."""
-import numpy as np
 import pytest
 
 from paper_2510_24175_amd import workloads as W

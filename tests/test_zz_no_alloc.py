@@ -7,7 +7,6 @@ the second).  Also: the limit and argument checks."""
 import ctypes
 import sys
 
-import numpy as np
 import pytest
 
 from paper_2510_24175_amd import workloads as W
