@@ -85,7 +85,7 @@ __device__ __forceinline__ void ct_cell_vc(const T *__restrict__ u, long long nc
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         v[d] = m[d] * ir;
-        cf[d] = fast_speed(rho, pr, bsq, b[d] * b[d], gamma, ir);
+        cf[d] = fast_speed(pr, bsq, b[d] * b[d], gamma, ir);
     }
 }
 

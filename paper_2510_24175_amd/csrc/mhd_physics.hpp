@@ -223,10 +223,10 @@ __device__ __forceinline__ void wenoz_pair(T v0, T v1, T v2, T v3, T v4, T &rgt,
     }
 }
 
-// Fast magnetosonic speed from rho, p, |B|^2 and B_n^2:
+// Fast magnetosonic speed from p, |B|^2, B_n^2 and 1/rho:
 // c_f^2 = (a^2 + b^2 + sqrt((a^2 - b^2)^2 + 4 a^2 (b^2 - b_n^2))) / 2.
 template <typename T>
-__device__ __forceinline__ T fast_speed(T rho, T p, T bsq, T bnsq, T gamma, T irho)
+__device__ __forceinline__ T fast_speed(T p, T bsq, T bnsq, T gamma, T irho)
 {
     const T a2 = gamma * p * irho;
     const T b2 = bsq * irho;
@@ -262,13 +262,6 @@ __device__ __forceinline__ void rstate_energy(RState<T> &s, const Phys<T> &ph)
     s.vb = s.u * s.bn + s.v1 * s.b1 + s.v2 * s.b2;
 }
 
-template <typename T>
-__device__ __forceinline__ void rstate_finish(RState<T> &s, const Phys<T> &ph)
-{
-    rstate_prepare(s);
-    rstate_energy(s, ph);
-}
-
 // physical normal flux (8 comps, slot 5 unused) and conserved vector
 template <typename T>
 __device__ __forceinline__ void rstate_flux(const RState<T> &s, T *f, T *c)
@@ -295,7 +288,7 @@ __device__ __forceinline__ void rstate_flux(const RState<T> &s, T *f, T *c)
 template <typename T>
 __device__ __forceinline__ T rstate_fast(const RState<T> &s, const Phys<T> &ph)
 {
-    return fast_speed(s.rho, s.p, s.bsq, s.bn * s.bn, ph.gamma, s.irho);
+    return fast_speed(s.p, s.bsq, s.bn * s.bn, ph.gamma, s.irho);
 }
 
 // HLL flux, Davis bounds clamped to the origin so one formula covers the

@@ -90,7 +90,7 @@ __device__ __forceinline__ bool cell_speeds(const T *u, double gamma, const doub
     bool ok = (rho > 0.0) & (rho < 1e300) & (p > 0.0) & (p < 1e300);
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
-        const double lam = __builtin_fabs(m[d] * ir) + fast_speed(rho, p, bsq, b[d] * b[d], gamma, ir);
+        const double lam = __builtin_fabs(m[d] * ir) + fast_speed(p, bsq, b[d] * b[d], gamma, ir);
         smax = __builtin_fmax(smax, lam * idx[d]);
         cmax = __builtin_fmax(cmax, lam);
     }
