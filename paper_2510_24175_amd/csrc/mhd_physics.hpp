@@ -181,10 +181,22 @@ template <int LIM, typename T> __device__ __forceinline__ T limited_slope(T a, T
 template <typename T>
 __device__ __forceinline__ void wenoz_pair(T v0, T v1, T v2, T v3, T v4, T &rgt, T &lft)
 {
-    const T e0 = (v0 + v2) - T(2) * v1, e1 = (v1 + v3) - T(2) * v2, e2 = (v2 + v4) - T(2) * v3;
-    const T G0 = T(0.5) * v0 - T(2) * v1 + T(1.5) * v2;
-    const T G1 = T(0.5) * (v1 - v3);
-    const T G2 = T(1.5) * v2 - T(2) * v3 + T(0.5) * v4;
+    T e0, e1, e2, G0, G1, G2;
+    if constexpr (sizeof(T) == 8) {
+        // from the two inner differences (11 operations instead of 14)
+        const T da = v2 - v1, db = v2 - v3;
+        e1 = -(da + db);
+        G1 = T(0.5) * (db - da);
+        e0 = (v0 - v1) + da;
+        e2 = (v4 - v3) + db;
+        G0 = T(0.5) * e0 + da;
+        G2 = T(0.5) * e2 + db;
+    } else {
+        e0 = (v0 + v2) - T(2) * v1, e1 = (v1 + v3) - T(2) * v2, e2 = (v2 + v4) - T(2) * v3;
+        G0 = T(0.5) * v0 - T(2) * v1 + T(1.5) * v2;
+        G1 = T(0.5) * (v1 - v3);
+        G2 = T(1.5) * v2 - T(2) * v3 + T(0.5) * v4;
+    }
     const T c = T(13.0 / 12.0);
     const T eps = Num<T>::weno_eps;
     // FP64 adds eps to G_k^2 first (one fused operation fewer per indicator);
