@@ -167,7 +167,8 @@ template <int LIM, typename T> __device__ __forceinline__ T limited_slope(T a, T
 // left, each scaled by 1 + tau5 / (beta_k + eps).
 //
 // FP64: the weights are multiplied through by (beta0+eps)(beta1+eps)(beta2+eps),
-// W_k = prod_{j != k}(beta_j + eps) (beta_k + eps + tau5), the linear weights
+// W_k = prod_{j != k}(beta_j + eps) (beta_k + eps + tau5) (formed as the triple product
+// plus tau5 times the pair product), the linear weights
 // are folded into the candidate deviations and the weight sums, and both faces
 // are normalised with one reciprocal of the product of the two weight sums,
 // the Newton-refined one (within an ulp).  That product lies between eps^6 and
@@ -208,9 +209,9 @@ __device__ __forceinline__ void wenoz_pair(T v0, T v1, T v2, T v3, T v4, T &rgt,
     const T tau = Num<T>::abs(B0 - B2);
     T nr, sr, nl, sl;
     if constexpr (sizeof(T) == 8) {
-        const T w0 = (B1 * B2) * (B0 + tau);
-        const T w1 = (B0 * B2) * (B1 + tau);
-        const T w2 = (B0 * B1) * (B2 + tau);
+        // W_k = B0 B1 B2 + tau5 prod_{j != k} B_j
+        const T p12 = B1 * B2, p02 = B0 * B2, p01 = B0 * B1, P = B0 * p12;
+        const T w0 = tau * p12 + P, w1 = tau * p02 + P, w2 = tau * p01 + P;
         // candidate deviations from v2 at the two faces, each scaled by its
         // linear weight ((1, 6, 3)/10 right, (3, 6, 1)/10 left)
         const T g0 = T(0.05) * G0, g1 = T(0.3) * G1, g2 = T(0.05) * G2;
